@@ -1,0 +1,83 @@
+"""GRAPE sweeps with Krylov propagation (oracle; test infrastructure only).
+
+Algorithm 1 with the propagators of Eq. B2 replaced by the Krylov propagator:
+  forward   psi_0 = |i>,  psi_j = exp(-i H_j dt) psi_{j-1},  H_j = H0 + u_j Hc  (Eqs. 1, 4, B1, B2)
+  overlap   beta = <f|psi_N>,  F = |beta|^2 = 1 - I                          (Eq. 2)
+  backward  lambda_N = |f>,  lambda_{j-1} = exp(+i H_j dt) lambda_j
+            (the paper's chi_j equals beta * lambda_j)
+  gradient  dI/du_j ~ -2 dt Im<chi_j|Hc|psi_j>                                (Eq. 5)
+            so dF/du_j = +2 dt Im(conj(beta) <lambda_j|Hc|psi_j>)
+  ascent    u <- u + eta * g / max_j |g_j|  (plain steepest ascent; the paper's
+            L-BFGS update of Algorithm 1 is not part of the hot path)
+Slices are numbered j = 1..N in the paper and 0..N-1 in arrays here.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import krylov
+from .model import Chain
+
+
+@dataclasses.dataclass
+class GradResult:
+    F: float
+    beta: complex
+    grad: np.ndarray          # (N,) dF/du_j
+    psi_N: np.ndarray
+    m_eff_fwd: np.ndarray     # (N,) Krylov dimension reached per forward slice
+    m_eff_bwd: np.ndarray     # (N,) per backward slice (entry 0 unused: no propagation at j=1)
+
+
+def forward(chain: Chain, u, psi0, dt, m, reorth=True, tol=None, keep=True):
+    """psi_0..psi_N (list) if ``keep`` else just psi_N, plus the m_eff per slice."""
+    psi = np.asarray(psi0, dtype=np.complex128)
+    states = [psi] if keep else None
+    m_eff = np.zeros(len(u), dtype=np.int64)
+    for j, uj in enumerate(u):
+        psi, lz = krylov.expv(lambda v, uj=uj: chain.apply(uj, v), psi, dt, m, reorth, tol,
+                              return_info=True)
+        m_eff[j] = lz.m_eff
+        if keep:
+            states.append(psi)
+    return (states if keep else psi), m_eff
+
+
+def overlap(target, psi_N) -> complex:
+    return complex(np.vdot(target, psi_N))
+
+
+def fidelity(chain: Chain, u, psi0, target, dt, m, reorth=True, tol=None) -> float:
+    psi_N, _ = forward(chain, u, psi0, dt, m, reorth, tol, keep=False)
+    return abs(overlap(target, psi_N)) ** 2
+
+
+def gradient(chain: Chain, u, psi0, target, dt, m, reorth=True, tol=None) -> GradResult:
+    """Fidelity and zeroth-order gradient, store-all forward then one backward sweep."""
+    u = np.asarray(u, dtype=np.float64)
+    N = u.shape[0]
+    states, m_fwd = forward(chain, u, psi0, dt, m, reorth, tol, keep=True)
+    beta = overlap(target, states[N])
+    lam = np.asarray(target, dtype=np.complex128)
+    g = np.zeros(N)
+    m_bwd = np.zeros(N, dtype=np.int64)
+    for j in range(N, 0, -1):                     # paper's slice index
+        bracket = np.vdot(lam, chain.apply_hc(states[j]))
+        g[j - 1] = 2.0 * dt * (np.conj(beta) * bracket).imag
+        if j > 1:
+            lam, lz = krylov.expv(lambda v, uj=u[j - 1]: chain.apply(uj, v), lam, -dt, m,
+                                  reorth, tol, return_info=True)
+            m_bwd[j - 1] = lz.m_eff
+    return GradResult(F=abs(beta) ** 2, beta=beta, grad=g, psi_N=states[N], m_eff_fwd=m_fwd,
+                      m_eff_bwd=m_bwd)
+
+
+def ascent_update(u, g, eta):
+    """u + eta * g / max|g| (no change when the gradient vanishes)."""
+    gmax = float(np.max(np.abs(g)))
+    if gmax == 0.0:
+        return np.array(u, dtype=np.float64)
+    return np.asarray(u, dtype=np.float64) + eta * np.asarray(g) / gmax

@@ -1,0 +1,151 @@
+"""Pins of the oracle's GRAPE sweeps and gradients (CPU only).
+
+The zeroth-order gradient of Eq. 5 is an approximation of the exact
+piecewise-constant gradient (Eqs. B3-B5), so it is pinned three ways:
+  * where it is exact (the control commutes with every slice Hamiltonian) it must
+    equal the exact gradient, which is itself pinned against finite differences;
+  * elsewhere its error against the exact gradient must shrink as dt^2;
+  * a small step along it must raise the fidelity (sign).
+The exact gradient is pinned by two independent derivative formulas and by
+central finite differences of dense propagation.
+"""
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import exact, grape, model
+from oracle.model import HC_SX, HC_SZ
+
+
+def dense_parts(L, J, Delta, kind, sites):
+    return model.xxz_dense(L, J, Delta), model.hc_dense(L, kind, sites)
+
+
+def chain_of(L, J, Delta, kind, sites):
+    return model.Chain(L, J, Delta, kind, sites)
+
+
+def test_small_workload_fidelity_matches_dense():
+    c = workloads.small()
+    ch = chain_of(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    r = grape.gradient(ch, c.u, c.psi0, c.target, c.dt, c.m)
+    H0, Hc = dense_parts(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    Fd = exact.dense_fidelity(H0, Hc, c.u, c.psi0, c.target, c.dt)
+    assert abs(r.F - Fd) < 1e-12
+    assert abs(np.linalg.norm(r.psi_N) - 1.0) < 1e-12
+    assert np.all(r.m_eff_fwd == c.m)
+
+
+@pytest.mark.parametrize("L,N,dt", [(4, 5, 0.3), (5, 4, 0.7)])
+def test_exact_derivative_two_formulas_and_fd(L, N, dt):
+    rng = np.random.default_rng(L)
+    H0, Hc = dense_parts(L, 1.0, 0.5, HC_SX, 1)
+    u = rng.uniform(-1, 1, N)
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    for uj in u[:2]:
+        H = H0 + uj * Hc
+        assert np.abs(exact.dU_daleckii_krein(H, Hc, dt) - exact.dU_van_loan(H, Hc, dt)).max() < 1e-13
+    F1, g1 = exact.exact_gradient_dense(H0, Hc, u, psi0, f, dt, method="dk")
+    F2, g2 = exact.exact_gradient_dense(H0, Hc, u, psi0, f, dt, method="vanloan")
+    assert np.abs(g1 - g2).max() < 1e-13
+    fd = exact.fd_gradient(lambda uu: exact.dense_fidelity(H0, Hc, uu, psi0, f, dt), u,
+                           range(N), h=1e-5)
+    fdv = np.array([fd[j] for j in range(N)])
+    assert np.abs(fdv - g1).max() < 1e-9 * max(1.0, np.abs(g1).max() * 1e3)
+    assert np.abs(fdv - g1).max() / np.abs(g1).max() < 1e-7
+
+
+def test_quadrature_exact_gradient_matches_dense():
+    L, N, dt, m = 6, 6, 0.2, 20
+    rng = np.random.default_rng(9)
+    H0, Hc = dense_parts(L, 1.0, 0.5, HC_SX, 1)
+    u = rng.uniform(-1, 1, N)
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    _, gd = exact.exact_gradient_dense(H0, Hc, u, psi0, f, dt)
+    ch = chain_of(L, 1.0, 0.5, HC_SX, 1)
+    _, gq = exact.exact_gradient_quadrature(ch, u, psi0, f, dt, m, slices=[0, 3, 5])
+    for j in [0, 3, 5]:
+        assert abs(gq[j] - gd[j]) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["no_drift", "total_sz"])
+def test_zeroth_order_is_exact_when_control_commutes(case):
+    """If [Hc, H_j] = 0 the time-averaged control operator (Eq. B6) is Hc itself,
+    so the zeroth-order gradient equals the exact one."""
+    L, N, dt = 5, 6, 0.4
+    rng = np.random.default_rng(21)
+    if case == "no_drift":
+        J, kind, sites = 0.0, HC_SX, 1 << 2
+    else:
+        J, kind, sites = 1.0, HC_SZ, (1 << L) - 1
+    H0, Hc = dense_parts(L, J, 0.5, kind, sites)
+    assert np.abs(H0 @ Hc - Hc @ H0).max() < 1e-14
+    u = rng.uniform(-1, 1, N)
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    _, g_exact = exact.exact_gradient_dense(H0, Hc, u, psi0, f, dt)
+    r = grape.gradient(chain_of(L, J, 0.5, kind, sites), u, psi0, f, dt, m=24)
+    assert np.abs(r.grad - g_exact).max() < 1e-12 * max(1.0, np.abs(g_exact).max())
+    assert np.abs(g_exact).max() > 1e-3   # the check is not vacuous
+
+
+def test_zeroth_order_error_is_second_order_in_dt():
+    """Error of Eq. 5 against the exact gradient falls ~4x per halving of dt.
+
+    The control is one fixed smooth function of time sampled at slice midpoints on
+    a fixed horizon T, so refining dt refines the same control problem."""
+    L, T = 6, 0.8
+    rng = np.random.default_rng(4)
+    H0, Hc = dense_parts(L, 1.0, 0.5, HC_SX, 1)
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    ch = chain_of(L, 1.0, 0.5, HC_SX, 1)
+    errs = []
+    for dt in [0.1, 0.05, 0.025]:
+        N = int(round(T / dt))
+        t_mid = (np.arange(N) + 0.5) * dt
+        u = np.sin(2.0 * t_mid) + 0.5 * np.cos(5.0 * t_mid)
+        _, ge = exact.exact_gradient_dense(H0, Hc, u, psi0, f, dt)
+        r = grape.gradient(ch, u, psi0, f, dt, m=24)
+        errs.append(np.abs(r.grad - ge).max())
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(3.5 < q < 4.5 for q in ratios), (errs, ratios)
+
+
+def test_gradient_ascent_direction_raises_fidelity():
+    c = workloads.small()
+    ch = chain_of(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    r = grape.gradient(ch, c.u, c.psi0, c.target, c.dt, c.m)
+    u2 = grape.ascent_update(c.u, r.grad, 0.05)
+    F2 = grape.fidelity(ch, u2, c.psi0, c.target, c.dt, c.m)
+    assert F2 > r.F
+    # first-order prediction of the change, with the exact gradient within O(dt)
+    H0, Hc = dense_parts(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    _, ge = exact.exact_gradient_dense(H0, Hc, c.u, c.psi0, c.target, c.dt)
+    assert np.linalg.norm(r.grad - ge) / np.linalg.norm(ge) < 0.1
+
+
+def test_costate_is_backward_propagated_target():
+    """lambda_j = U_{j+1}^dag ... U_N^dag f, checked through <lambda_0|psi_0> = beta."""
+    L, N, dt = 6, 7, 0.15
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-1, 1, N)
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    ch = chain_of(L, 1.0, 0.5, HC_SX, 1)
+    from oracle import krylov
+    lam = f.copy()
+    for j in range(N, 0, -1):
+        lam = krylov.expv(lambda v, uj=u[j - 1]: ch.apply(uj, v), lam, -dt, 24)
+    r = grape.gradient(ch, u, psi0, f, dt, m=24)
+    assert abs(np.vdot(lam, psi0) - r.beta) < 1e-12
+
+
+def test_ascent_update():
+    u = np.array([0.5, -0.25, 0.0])
+    g = np.array([0.1, -0.4, 0.2])
+    assert np.allclose(grape.ascent_update(u, g, 0.1), u + 0.1 * g / 0.4)
+    assert np.array_equal(grape.ascent_update(u, np.zeros(3), 0.1), u)
