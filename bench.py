@@ -1,0 +1,235 @@
+"""Benchmark of the K-GRAPE hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload (the adjoint form's chain): open XXZ chain L=20 (D = 1,048,576),
+J=1, Delta=1, control S^x on site 1, N=400 slices, dt=0.05, Krylov m=20 with
+full re-orthogonalisation, random-phase psi0 and target, controls U(-1,1)
+(seed 2), sqrt(N) checkpointing every 20 slices.  One step = one GRAPE
+gradient evaluation: forward sweep, overlap, segment recomputation, backward
+sweep and the N gradient brackets, all on the GPU.  The headline value is
+gradient evaluations per second of the mixed-precision path (complex64
+vectors, FP64 scalars); the FP64 path (complex128) is timed beside it on the
+same inputs and the error of mixed vs FP64 is reported.
+
+Prints ONE JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GRAPE gradient evals/sec and H·v GB/s at L=20; mixed vs FP64 at stated error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def gpu_inputs(c, dtype, torch):
+    dev = torch.device("cuda:0")
+    u = torch.tensor(c.u, dtype=torch.float64, device=dev)
+    psi0 = torch.tensor(c.psi0, dtype=dtype, device=dev)
+    f = torch.tensor(c.target, dtype=dtype, device=dev)
+    return u, psi0, f
+
+
+def time_gradients(kg, torch, c, dtype, ckpt, steps, warmup, profile_every=0):
+    h = kg.XXZ(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    k = kg.Krylov(c.m, reorth=True)
+    u, psi0, f = gpu_inputs(c, dtype, torch)
+    ws = kg.Workspace(h, k, dtype)
+    states = kg.new_states(h, c.N, ckpt, dtype)
+    grad = torch.empty(c.N, dtype=torch.float64, device=u.device)
+    beta = torch.empty(2, dtype=torch.float64, device=u.device)
+    F = torch.empty((), dtype=torch.float64, device=u.device)
+
+    def step():
+        kg.grape_gradient(h, u, c.dt, k, psi0, f, ckpt_every=ckpt, states=states, grad=grad,
+                          beta=beta, F=F, workspace=ws)
+
+    for i in range(warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{warmup} done")
+    prof = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if profile_every:
+        prof = kg.profile(sample_every=profile_every, max_launches=1 << 20)
+        prof.__enter__()
+    for i in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if prof is not None:
+        prof.__exit__(None, None, None)
+    log(f"timed {steps} steps ({dtype}) in {t1 - t0:.3f} s")
+    return (t1 - t0) / steps, float(F.cpu()), grad.cpu().numpy(), (prof.result if prof else None)
+
+
+def time_hv(kg, torch, L, dtype, reps=50):
+    h = kg.XXZ(L, 1.0, 0.5)
+    D = 1 << L
+    g = torch.Generator(device="cuda")
+    g.manual_seed(L)
+    v = torch.randn(D, dtype=dtype, device="cuda", generator=g)
+    w = torch.empty_like(v)
+    for _ in range(3):
+        kg.xxz_apply(h, 0.3, v, out=w)
+    torch.cuda.synchronize()
+    with kg.profile(sample_every=1, max_launches=reps) as p:
+        for _ in range(reps):
+            kg.xxz_apply(h, 0.3, v, out=w)
+    r = p.result["hv"]
+    per = r["ms"] / r["launches"] * 1e-3
+    return {"L": L, "dtype": str(dtype).replace("torch.", ""), "us_per_launch": per * 1e6,
+            "algorithmic_GBps": (r["bytes"] / r["launches"]) / per / 1e9}
+
+
+def cpu_baseline(c, budget_s=20.0):
+    """The oracle (NumPy/SciPy FP64) on a bounded prefix of the same workload:
+    forward Krylov propagations of the first slices, extrapolated to the
+    oracle's full gradient (2N-1 propagations + N brackets, store-all)."""
+    from oracle import grape as og  # noqa: F401
+    from oracle import krylov as ok
+    from oracle import model as om
+
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = 1
+    t_build = time.perf_counter()
+    ch = om.Chain(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    t_build = time.perf_counter() - t_build
+    psi = c.psi0.copy()
+    n_done = 0
+    t0 = time.perf_counter()
+    while True:
+        psi = ok.expv(lambda v, uj=c.u[n_done]: ch.apply(uj, v), psi, c.dt, c.m, True)
+        n_done += 1
+        if time.perf_counter() - t0 > budget_s or n_done >= c.N:
+            break
+    t_call = (time.perf_counter() - t0) / n_done
+    tb = time.perf_counter()
+    np.vdot(c.target, ch.apply_hc(psi))
+    t_bracket = time.perf_counter() - tb
+    per_grad = t_call * (2 * c.N - 1) + t_bracket * c.N
+    return {"value": 1.0 / per_grad, "unit": "gradient evals/s", "cores": int(blas_threads),
+            "kind": "oracle",
+            "sample": f"{n_done} Krylov propagations (m={c.m}, L={c.L}) of the first slices, "
+                      f"{t_call:.2f} s each, plus one bracket; extrapolated to 2N-1={2 * c.N - 1} "
+                      f"propagations and N={c.N} brackets per gradient (sparse-matrix build "
+                      f"{t_build:.1f} s excluded)",
+            "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--profile-every", type=int, default=4,
+                    help="time every n-th Krylov call's kernels with HIP events (0: off)")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the chain's "
+              "slices are sequential and this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2010_03598_amd as kg
+    import workloads
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    c = workloads.adjoint()
+    ckpt = workloads.ADJOINT_CKPT_EVERY
+    log(f"workload: L={c.L} N={c.N} m={c.m} dt={c.dt} Delta={c.Delta} ckpt_every={ckpt}")
+
+    sec64, F64, g64, prof = time_gradients(kg, torch, c, torch.complex64, ckpt, args.steps,
+                                           args.warmup, args.profile_every)
+    sec128, F128, g128, _ = time_gradients(kg, torch, c, torch.complex128, ckpt, args.fp64_steps,
+                                           0, 0)
+    errF = abs(F64 - F128) / abs(F128)
+    errg = float(np.linalg.norm(g64 - g128) / np.linalg.norm(g128))
+    errg_inf = float(np.abs(g64 - g128).max() / np.abs(g128).max())
+
+    # dominant kernel: the class with the largest sampled time
+    dom = max(("pass_a", "pass_b", "combine", "bracket", "overlap"), key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    per_launch_s = d["ms"] / d["launches"] * 1e-3
+    bytes_per_launch = d["bytes"] / d["launches"]
+    achieved = bytes_per_launch / per_launch_s / 1e9
+    classes = {k: {"launches_timed": v["launches"],
+                   "avg_us": (v["ms"] / v["launches"] * 1e3) if v["launches"] else None,
+                   "avg_algorithmic_GB": (v["bytes"] / v["launches"] / 1e9) if v["launches"] else None,
+                   "GBps": (v["bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] else None}
+               for k, v in prof.items() if v["launches"]}
+
+    hv20 = time_hv(kg, torch, 20, torch.complex64)
+    hv24 = time_hv(kg, torch, 24, torch.complex64, reps=20)
+    hv24_128 = time_hv(kg, torch, 24, torch.complex128, reps=20)
+
+    cpu = None if args.no_cpu else cpu_baseline(c, args.cpu_budget)
+
+    out = {
+        "metric": METRIC,
+        "value": 1.0 / sec64,
+        "unit": "gradient evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64",
+        "data": "synthetic",
+        "config": {"workload": "adjoint: open XXZ L=20 (D=2^20), J=1, Delta=1, Hc=Sx site 1, "
+                               "N=400, dt=0.05, m=20 full reorth, ckpt every 20, seed 2",
+                   "L": c.L, "N": c.N, "m": c.m, "dt": c.dt, "ckpt_every": ckpt,
+                   "precision": "complex64 vectors, FP64 scalars", "parallelism": "1 GPU"},
+        "fp64": {"value": 1.0 / sec128, "unit": "gradient evals/s", "ms_per_step": sec128 * 1e3,
+                 "steps": args.fp64_steps},
+        "mixed_vs_fp64_error": {"F_rel": errF, "grad_rel_l2": errg, "grad_rel_inf": errg_inf,
+                                "F_fp64": F128},
+        "hv": {"L20_c64": hv20, "L24_c64": hv24, "L24_c128": hv24_128,
+               "peak_GBps": HBM_PEAK_GBS},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "avg_us": per_launch_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "sampled_launches": d["launches"]},
+        "kernels": classes,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,195 @@
+/*
+ * kgrape.h - C ABI of the MI355X (gfx950) K-GRAPE library (libkgrape.so).
+ *
+ * K-GRAPE (Larocca & Wisniacki, arXiv 2010.03598) is GRAPE with every
+ * sub-propagator applied by a Krylov (Lanczos) approximation.  This library
+ * runs its hot path on one GPU:
+ *   xxz_apply       w = (H0 + u Hc) v                       (Sec. III.A, Eqs. 1, 6, 10)
+ *   krylov_expv     v_out ~ exp(-i t (H0 + u Hc)) v_in      (App. A, Algorithm 2, Eqs. A1-A3)
+ *   grape_forward   psi_j = U_j psi_{j-1}, beta = <f|psi_N>, F = |beta|^2
+ *                                                           (Algorithm 1, Eqs. 2, 4, B1, B2)
+ *   grape_gradient  dF/du_j = 2 dt Im(conj(beta) <lambda_j|Hc|psi_j>)
+ *                   with lambda_N = f, lambda_{j-1} = U_j^dagger lambda_j   (Eq. 5, Algorithm 1)
+ *   grape_ascent_update  u <- u + eta g / max|g|            (steepest ascent, Algorithm 1 update)
+ *
+ * Model.  Open chain of L spins 1/2, S = sigma/2:
+ *   H0 = J sum_{i=1}^{L-1} (Sx_i Sx_{i+1} + Sy_i Sy_{i+1} + Delta Sz_i Sz_{i+1}).
+ * The paper's Pauli form (J_p/2) sum(sigma sigma + alpha_z sigma^z sigma^z) is
+ * J = 2 J_p, Delta = alpha_z here.  Control operators: KG_HC_SX = S^x on one
+ * site; KG_HC_SZ = sum of S^z over a set of sites (the paper's control is
+ * J_p (S^z_1 + S^z_L), i.e. KG_HC_SZ on {1, L} with u scaled by J_p).
+ *
+ * Basis.  Spin up = bit 0, spin down = bit 1, site 1 is the most significant
+ * bit: the amplitude of a product state sits at index s = sum_i b_i 2^(L-i)
+ * (the paper's ordering of computational basis states, Sec. III.A).
+ *
+ * Data.  State vectors are D = 2^L complex amplitudes, interleaved (re, im),
+ * contiguous: complex128 (16 B) for KG_C128, complex64 (8 B) for KG_C64.  All
+ * vector, control, output and workspace pointers are DEVICE pointers owned by
+ * the caller; vectors must be 16-byte aligned, workspaces 256-byte aligned.
+ * Controls u and every scalar result (F, beta, gradient) are FP64.
+ *
+ * Precision KG_C64 keeps vectors in complex64 and applies H in FP32, while the
+ * Lanczos scalars (alpha, beta, norms), every dot product (re-orthogonalisation
+ * sums, overlap, gradient bracket), the small exponential and the basis
+ * combination run in FP64 (one rounding to complex64 per stored vector).
+ *
+ * Conventions of every entry point.
+ *   - Host-side validation runs first; on failure nothing is launched, the
+ *     status is negative and kg_last_error() names the argument.
+ *   - Nothing allocates device memory; scratch comes from the caller's
+ *     workspace (size from kg_workspace_bytes).  No call synchronises the
+ *     stream; results are ready when the stream reaches them.
+ *   - `stream` is a hipStream_t (NULL = the default stream).
+ *   - Inputs are never renormalised: psi0 and the target should have unit norm.
+ *   - Calls that share a workspace must not run concurrently.
+ *   - Lanczos breakdown (an invariant Krylov space) is not an error: the call
+ *     uses the reached dimension m_eff < m, reported through m_eff_dev.
+ */
+#ifndef KGRAPE_H
+#define KGRAPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t kg_status;
+#define KG_OK 0
+#define KG_EINVAL (-1)      /* bad argument: see kg_last_error() */
+#define KG_EWORKSPACE (-3)  /* workspace or state buffer too small / misaligned */
+#define KG_EDEVICE (-4)     /* a HIP runtime call failed (launch error, no device) */
+
+#define KG_C128 0           /* complex128 vectors, FP64 everything */
+#define KG_C64 1            /* complex64 vectors, FP64 scalars */
+
+#define KG_HC_SX 0          /* S^x on exactly one site */
+#define KG_HC_SZ 1          /* sum of S^z over a non-empty set of sites */
+
+#define KG_MAX_M 64         /* largest Krylov dimension */
+#define KG_MIN_L 2
+#define KG_MAX_L 30
+
+/* One open XXZ chain.  hc_sites: bit (i-1) set <=> site i (1..L) carries the
+ * control operator; KG_HC_SX needs exactly one bit. */
+typedef struct kg_xxz {
+  int32_t L;
+  int32_t hc_kind;
+  double J;
+  double Delta;
+  uint64_t hc_sites;
+} kg_xxz;
+
+/* Krylov options.  m: dimension (1..KG_MAX_M).  reorth: 1 = each candidate
+ * H v_k is orthogonalised against all previous basis vectors (full classical
+ * Gram-Schmidt, App. A), 0 = against the last two only (plain Lanczos,
+ * Algorithm 2).  breakdown_tol: relative threshold; the basis stops at step k
+ * when ||w_{k+1}|| <= tol * max(1, max_{i<=k}(|alpha_i| + beta_i)); 0 selects
+ * 64 * (unit roundoff of the vector type). */
+typedef struct kg_krylov {
+  int32_t m;
+  int32_t reorth;
+  double breakdown_tol;
+} kg_krylov;
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char* kg_last_error(void);
+
+/* Library ABI version (monotonic integer). */
+int32_t kg_version(void);
+
+/* Bytes of workspace that krylov_expv, grape_forward and grape_gradient need
+ * for this chain, Krylov dimension and precision: the m-1 Krylov basis
+ * vectors, one costate vector, and a fixed block of scalars and reduction
+ * partials.  Returns 0 for invalid arguments. */
+size_t kg_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec);
+
+/* Bytes of the forward-state buffer of grape_forward/grape_gradient.
+ * ckpt_every = 0 stores psi_1..psi_N (N vectors).  ckpt_every = c in 1..N
+ * stores psi_c, psi_2c, ... below the last segment (ceil(N/c)-1 vectors) plus
+ * a segment buffer of c vectors, and recomputes each segment from its
+ * checkpoint during the backward sweep (sqrt(N) checkpointing when c ~ sqrt(N)).
+ * Returns 0 for invalid arguments. */
+size_t kg_states_bytes(const kg_xxz* h, int32_t N, int32_t ckpt_every, int32_t prec);
+
+/* w = (H0 + u Hc) v  (Eqs. 1, 6, 10; matrix-free).  v and w: D amplitudes of
+ * type `prec`; they must not overlap.  Errors: KG_EINVAL, KG_EDEVICE. */
+kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void* w,
+                    void* stream);
+
+/* v_out ~ exp(-i t (H0 + u Hc)) v_in by an m-dimensional Lanczos basis
+ * (App. A, Algorithm 2) and the exponential of the tridiagonal projection
+ * (Eqs. A1-A3): v_out = ||v_in|| V^T exp(-i t T) e_1.  v_out may equal v_in
+ * (in place); otherwise they must not overlap.  A zero input gives a zero
+ * output (m_eff = 0).  m_eff_dev (nullable): device int32 that receives the
+ * dimension reached.  Errors: KG_EINVAL, KG_EWORKSPACE, KG_EDEVICE. */
+kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, int32_t prec,
+                      const void* v_in, void* v_out, void* ws, size_t ws_bytes,
+                      int32_t* m_eff_dev, void* stream);
+
+/* Forward sweep of Algorithm 1 (Eqs. 2, 4, B1, B2): psi_j = exp(-i dt H_j)
+ * psi_{j-1}, H_j = H0 + u_j Hc, j = 1..N, with u_dev[j-1] = u_j.  Writes
+ * beta = <target|psi_N> to beta_dev[0..1] (re, im) and F = |beta|^2 to
+ * *F_dev.  `states` (kg_states_bytes) receives the stored forward states in
+ * the layout of ckpt_every; psi_N is stored in it.  Errors: KG_EINVAL,
+ * KG_EWORKSPACE, KG_EDEVICE. */
+kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                        const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                        double* F_dev, double* beta_dev, void* states, int32_t ckpt_every,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Fidelity and zeroth-order GRAPE gradient (Eq. 5, Algorithm 1):
+ *   grad_dev[j-1] = dF/du_j ~ 2 dt Im(conj(beta) <lambda_j|Hc|psi_j>),
+ *   lambda_N = target, lambda_{j-1} = exp(+i dt H_j) lambda_j.
+ * (The paper's infidelity gradient is -grad, its chi_j is beta lambda_j.)
+ * states_valid = 1 reuses the states and beta of a preceding grape_forward
+ * with the same arguments (no forward sweep); 0 runs the forward sweep first.
+ * With ckpt_every > 0 the segments between checkpoints are recomputed; the
+ * result is bit-identical to ckpt_every = 0.  F_dev, beta_dev as in
+ * grape_forward.  Errors: KG_EINVAL, KG_EWORKSPACE, KG_EDEVICE. */
+kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                         const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                         double* F_dev, double* beta_dev, double* grad_dev, void* states,
+                         int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Steepest-ascent update u_j <- u_j + eta * g_j / max_i |g_i| on the device
+ * (u unchanged when g = 0).  N >= 1.  Errors: KG_EINVAL, KG_EDEVICE. */
+kg_status grape_ascent_update(double* u_dev, const double* grad_dev, int32_t N, double eta,
+                              void* stream);
+
+/* ---------------------------------------------------------------- diagnostics
+ * Integer index maps of H0 for s = s0 .. s0+count-1 (L <= 30):
+ *   n_anti[i]       = number of antiparallel nearest-neighbour bonds of s,
+ *   partner_mask[i] = bit p set <=> bond (p, p+1) is antiparallel, i.e. the
+ *                     hopping term couples s to s ^ (3 << p).
+ * Device outputs.  Errors: KG_EINVAL, KG_EDEVICE. */
+kg_status kg_debug_index_map(int32_t L, uint32_t s0, uint32_t count, int32_t* n_anti_dev,
+                             uint32_t* partner_mask_dev, void* stream);
+
+/* Sampled kernel timing, for benchmarks (not thread-safe, one session at a
+ * time).  Between kg_profile_begin and kg_profile_end, every sample_every-th
+ * Krylov call (and every sample_every-th overlap, bracket and xxz_apply
+ * launch) records a pair of HIP events on its stream around each kernel, for
+ * at most max_launches kernels.  kg_profile_end waits for the last event and
+ * fills, per kernel class (KG_PROF_NCLASS entries each; NULL skips an array):
+ * launches timed, summed duration in ms, and summed algorithmic bytes
+ * (vectors each kernel must read and write once, no cache re-reads).
+ * Errors: KG_EINVAL, KG_EDEVICE. */
+#define KG_PROF_PASS_A 0    /* Lanczos pass A: H v_k and the projection dots */
+#define KG_PROF_PASS_B 1    /* Lanczos pass B: new basis vector and its norm */
+#define KG_PROF_COMBINE 2   /* v_out = beta0 V^T exp(-itT) e_1 */
+#define KG_PROF_BRACKET 3   /* gradient bracket <lambda|Hc|psi> */
+#define KG_PROF_OVERLAP 4   /* <f|psi_N> */
+#define KG_PROF_HV 5        /* xxz_apply */
+#define KG_PROF_NCLASS 6
+kg_status kg_profile_begin(int32_t sample_every, int32_t max_launches);
+kg_status kg_profile_end(int64_t* launches, double* ms, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KGRAPE_H */

@@ -1,0 +1,100 @@
+"""ctypes view of libkgrape.so (the C ABI declared in include/kgrape.h).
+
+Loading fails loudly: there is no fallback implementation of any entry point.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libkgrape.so")
+
+KG_OK = 0
+KG_EINVAL = -1
+KG_EWORKSPACE = -3
+KG_EDEVICE = -4
+
+KG_C128 = 0
+KG_C64 = 1
+
+KG_HC_SX = 0
+KG_HC_SZ = 1
+
+KG_MAX_M = 64
+KG_MIN_L = 2
+KG_MAX_L = 30
+
+
+class KgXxz(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("hc_kind", ctypes.c_int32), ("J", ctypes.c_double),
+                ("Delta", ctypes.c_double), ("hc_sites", ctypes.c_uint64)]
+
+
+class KgKrylov(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int32), ("reorth", ctypes.c_int32),
+                ("breakdown_tol", ctypes.c_double)]
+
+
+class KgError(RuntimeError):
+    def __init__(self, fn: str, status: int, message: str):
+        super().__init__(f"{fn} failed with status {status}: {message}")
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_U32 = ctypes.c_uint32
+_D = ctypes.c_double
+_SZ = ctypes.c_size_t
+_PX = ctypes.POINTER(KgXxz)
+_PK = ctypes.POINTER(KgKrylov)
+
+# name -> (restype, argtypes); mirrors include/kgrape.h
+SIGNATURES = {
+    "kg_last_error": (ctypes.c_char_p, []),
+    "kg_version": (_I32, []),
+    "kg_workspace_bytes": (_SZ, [_PX, _PK, _I32]),
+    "kg_states_bytes": (_SZ, [_PX, _I32, _I32, _I32]),
+    "xxz_apply": (_I32, [_PX, _D, _I32, _P, _P, _P]),
+    "krylov_expv": (_I32, [_PX, _D, _D, _PK, _I32, _P, _P, _P, _SZ, _P, _P]),
+    "grape_forward": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _I32, _P, _SZ, _P]),
+    "grape_gradient": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _P, _I32, _I32,
+                              _P, _SZ, _P]),
+    "grape_ascent_update": (_I32, [_P, _P, _I32, _D, _P]),
+    "kg_debug_index_map": (_I32, [_I32, _U32, _U32, _P, _P, _P]),
+    "kg_profile_begin": (_I32, [_I32, _I32]),
+    "kg_profile_end": (_I32, [_P, _P, _P]),
+}
+
+PROF_CLASSES = ["pass_a", "pass_b", "combine", "bracket", "overlap", "hv"]
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2010_03598_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().kg_last_error().decode()
+
+
+def check(fn: str, status: int) -> None:
+    if status != KG_OK:
+        raise KgError(fn, status, last_error())

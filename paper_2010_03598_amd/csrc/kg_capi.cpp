@@ -1,0 +1,549 @@
+// C ABI of libkgrape (declared in include/kgrape.h): argument validation,
+// workspace carving and the orchestration of the GRAPE sweeps (Algorithm 1)
+// on top of the kernels in kg_kernels.hip.  No entry point allocates device
+// memory or synchronises the stream.
+
+#include "kgrape.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "kg_internal.h"
+
+namespace kg {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+kg_status fail(kg_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+kg_status ok() {
+  g_last_error.clear();
+  return KG_OK;
+}
+
+kg_status hip_fail(hipError_t e, const char* where) {
+  return fail(KG_EDEVICE, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+#define KG_CHECK(x)                                  \
+  do {                                               \
+    kg_status st_ = (x);                             \
+    if (st_ != KG_OK) return st_;                    \
+  } while (0)
+
+#define KG_HIP(x, where)                             \
+  do {                                               \
+    hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+kg_status check_xxz(const kg_xxz* h) {
+  if (!h) return fail(KG_EINVAL, "h is NULL");
+  if (h->L < KG_MIN_L || h->L > KG_MAX_L)
+    return fail(KG_EINVAL, "L=%d outside [%d, %d]", h->L, KG_MIN_L, KG_MAX_L);
+  if (!isfinite(h->J) || !isfinite(h->Delta)) return fail(KG_EINVAL, "J and Delta must be finite");
+  if (h->hc_kind != KG_HC_SX && h->hc_kind != KG_HC_SZ)
+    return fail(KG_EINVAL, "unknown hc_kind %d", h->hc_kind);
+  if (h->hc_sites == 0) return fail(KG_EINVAL, "hc_sites is empty");
+  if (h->hc_sites >> h->L) return fail(KG_EINVAL, "hc_sites names a site beyond L=%d", h->L);
+  if (h->hc_kind == KG_HC_SX && __builtin_popcountll(h->hc_sites) != 1)
+    return fail(KG_EINVAL, "KG_HC_SX needs exactly one site");
+  return KG_OK;
+}
+
+kg_status check_krylov(const kg_krylov* k) {
+  if (!k) return fail(KG_EINVAL, "k is NULL");
+  if (k->m < 1 || k->m > KG_MAX_M) return fail(KG_EINVAL, "m=%d outside [1, %d]", k->m, KG_MAX_M);
+  if (k->reorth != 0 && k->reorth != 1) return fail(KG_EINVAL, "reorth must be 0 or 1");
+  if (!(k->breakdown_tol >= 0.0) || !isfinite(k->breakdown_tol))
+    return fail(KG_EINVAL, "breakdown_tol must be finite and >= 0");
+  return KG_OK;
+}
+
+kg_status check_prec(int32_t prec) {
+  if (prec != KG_C128 && prec != KG_C64) return fail(KG_EINVAL, "unknown precision %d", prec);
+  return KG_OK;
+}
+
+kg_status check_vec(const void* p, int32_t prec, const char* name) {
+  if (!p) return fail(KG_EINVAL, "%s is NULL", name);
+  const uintptr_t a = prec == KG_C128 ? 16 : 8;
+  if ((uintptr_t)p % a) return fail(KG_EINVAL, "%s is not %d-byte aligned", name, (int)a);
+  return KG_OK;
+}
+
+bool overlap(const void* a, const void* b, size_t n) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return x < y + n && y < x + n;
+}
+
+double default_tol(int32_t prec) { return 64.0 * (prec == KG_C128 ? ldexp(1.0, -52) : ldexp(1.0, -23)); }
+
+HvArgs make_hv(const kg_xxz* h, const double* u_ptr, double u_val) {
+  HvArgs a;
+  memset(&a, 0, sizeof(a));
+  a.L = h->L;
+  a.hc_kind = h->hc_kind;
+  if (h->hc_kind == KG_HC_SX) {
+    const int site = __builtin_ctzll(h->hc_sites) + 1;
+    a.hc_bit = h->L - site;
+  } else {
+    uint32_t mask = 0;
+    int cnt = 0;
+    for (int i = 1; i <= h->L; ++i) {
+      if ((h->hc_sites >> (i - 1)) & 1ull) {
+        mask |= 1u << (h->L - i);
+        ++cnt;
+      }
+    }
+    a.sz_mask = mask;
+    a.sz_count = cnt;
+  }
+  a.half_J = 0.5 * h->J;
+  a.c_zz = 0.25 * h->J * h->Delta;
+  a.u_ptr = u_ptr;
+  a.u_val = u_val;
+  return a;
+}
+
+kg_status carve(void* ws, size_t ws_bytes, const kg_xxz* h, const kg_krylov* k, int32_t prec,
+                Workspace* out) {
+  if (!ws) return fail(KG_EWORKSPACE, "workspace is NULL");
+  if ((uintptr_t)ws % 256) return fail(KG_EWORKSPACE, "workspace is not 256-byte aligned");
+  const size_t need = kg_workspace_bytes(h, k, prec);
+  if (ws_bytes < need)
+    return fail(KG_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+  char* p = static_cast<char*>(ws);
+  out->st = reinterpret_cast<KState*>(p);
+  p += align_up(sizeof(KState), 256);
+  out->partials = reinterpret_cast<cplx_d*>(p);
+  p += align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256);
+  out->gpartials = reinterpret_cast<cplx_d*>(p);
+  p += align_up(sizeof(cplx_d) * kMaxGroups * kMaxScal, 256);
+  const size_t vb = vec_bytes(h->L, prec);
+  out->basis = p;
+  p += align_up(vb * (size_t)(k->m > 1 ? k->m - 1 : 0), 256);
+  out->lam = p;
+  return KG_OK;
+}
+
+// Where the forward states live in the caller's state buffer.
+struct States {
+  int N = 0, c = 0, nseg = 1, clast = 0;
+  char* base = nullptr;
+  size_t vb = 0;
+  const void* psi0 = nullptr;
+
+  void* ckpt(int q) const { return base + (size_t)(q - 1) * vb; }           // psi_{q c}, q >= 1
+  void* buf(int i) const { return base + (size_t)(nseg - 1 + i) * vb; }    // segment slot i
+  // slot that receives psi_j (j >= 1) during the forward sweep
+  void* fwd(int j) const {
+    if (c == 0) return base + (size_t)(j - 1) * vb;
+    if (j > clast) return buf(j - clast - 1);
+    if (j % c == 0) return ckpt(j / c);
+    return buf(j % c - 1);
+  }
+  const void* fwd_in(int j) const { return j == 0 ? psi0 : fwd(j); }
+  // slot of psi_j during the backward sweep of its segment (after recomputation)
+  const void* bwd(int j) const {
+    if (c == 0) return base + (size_t)(j - 1) * vb;
+    const int q = (j - 1) / c, cs = q * c, len = (N - cs < c) ? N - cs : c;
+    if (j < cs + len || q == nseg - 1) return buf(j - cs - 1);
+    return ckpt(q + 1);
+  }
+};
+
+States make_states(int N, int c, void* base, size_t vb, const void* psi0) {
+  States s;
+  s.N = N;
+  s.c = c;
+  s.base = static_cast<char*>(base);
+  s.vb = vb;
+  s.psi0 = psi0;
+  if (c > 0) {
+    s.nseg = (N + c - 1) / c;
+    s.clast = (s.nseg - 1) * c;
+  }
+  return s;
+}
+
+struct SweepArgs {
+  const kg_xxz* h;
+  const double* u_dev;
+  int N;
+  double dt;
+  const kg_krylov* k;
+  int prec;
+  const void* psi0;
+  const void* target;
+  Geo geo;
+  Workspace ws;
+  hipStream_t stream;
+};
+
+KrylovCall krylov_call(const SweepArgs& a, int j, double t, const void* in, void* out) {
+  KrylovCall c;
+  c.hv = make_hv(a.h, a.u_dev + (j - 1), 0.0);
+  c.geo = a.geo;
+  c.prec = a.prec;
+  c.m = a.k->m;
+  c.reorth = a.k->reorth;
+  c.t = t;
+  c.tol = a.k->breakdown_tol > 0.0 ? a.k->breakdown_tol : default_tol(a.prec);
+  c.v_in = in;
+  c.v_out = out;
+  c.m_eff_out = nullptr;
+  return c;
+}
+
+kg_status forward_sweep(const SweepArgs& a, const States& S, double* F_dev, double* beta_dev) {
+  for (int j = 1; j <= a.N; ++j) {
+    const KrylovCall c = krylov_call(a, j, a.dt, S.fwd_in(j - 1), S.fwd(j));
+    KG_HIP(launch_krylov(c, a.ws, a.stream), "forward sweep");
+  }
+  Profiler* prof = profiler_for_launch();
+  if (prof) profiler_start(prof, a.stream);
+  KG_HIP(launch_overlap(a.prec, a.geo.D, a.target, S.fwd(a.N), a.ws, F_dev, beta_dev, a.stream),
+         "overlap");
+  if (prof) profiler_stop(prof, a.stream, kProfOverlap, 2.0 * vec_bytes(a.h->L, a.prec));
+  return KG_OK;
+}
+
+kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta_dev,
+                         double* grad_dev) {
+  const HvArgs hc = make_hv(a.h, nullptr, 0.0);
+  const void* lam = a.target;
+  for (int q = S.nseg - 1; q >= 0; --q) {
+    const int cs = (S.c == 0) ? 0 : q * S.c;
+    const int len = (S.c == 0) ? a.N : ((a.N - cs < S.c) ? a.N - cs : S.c);
+    if (S.c > 0 && q < S.nseg - 1) {
+      // recompute psi_{cs+1} .. psi_{cs+len-1} from the checkpoint psi_cs
+      const void* in = (q == 0) ? a.psi0 : S.ckpt(q);
+      for (int i = 1; i < len; ++i) {
+        const KrylovCall c = krylov_call(a, cs + i, a.dt, in, S.buf(i - 1));
+        KG_HIP(launch_krylov(c, a.ws, a.stream), "segment recomputation");
+        in = S.buf(i - 1);
+      }
+    }
+    for (int j = cs + len; j > cs; --j) {
+      Profiler* prof = profiler_for_launch();
+      if (prof) profiler_start(prof, a.stream);
+      KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.bwd(j), a.dt, beta_dev, a.ws,
+                            grad_dev + (j - 1), a.stream),
+             "gradient bracket");
+      if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * vec_bytes(a.h->L, a.prec));
+      if (j > 1) {
+        const KrylovCall c = krylov_call(a, j, -a.dt, lam, a.ws.lam);
+        KG_HIP(launch_krylov(c, a.ws, a.stream), "backward sweep");
+        lam = a.ws.lam;
+      }
+    }
+  }
+  return KG_OK;
+}
+
+kg_status check_sweep(const kg_xxz* h, const double* u_dev, int32_t N, double dt, const kg_krylov* k,
+                      int32_t prec, const void* psi0, const void* target, void* states,
+                      int32_t ckpt_every) {
+  KG_CHECK(check_xxz(h));
+  KG_CHECK(check_krylov(k));
+  KG_CHECK(check_prec(prec));
+  if (!u_dev) return fail(KG_EINVAL, "u_dev is NULL");
+  if ((uintptr_t)u_dev % 8) return fail(KG_EINVAL, "u_dev is not 8-byte aligned");
+  if (N < 1) return fail(KG_EINVAL, "N=%d must be >= 1", N);
+  if (!isfinite(dt)) return fail(KG_EINVAL, "dt must be finite");
+  if (ckpt_every < 0 || ckpt_every > N)
+    return fail(KG_EINVAL, "ckpt_every=%d outside [0, N=%d]", ckpt_every, N);
+  KG_CHECK(check_vec(psi0, prec, "psi0"));
+  KG_CHECK(check_vec(target, prec, "target"));
+  KG_CHECK(check_vec(states, prec, "states"));
+  return KG_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------- sampled kernel timing
+
+struct Profiler {
+  int sample_every = 1;
+  long calls = 0;
+  long launches = 0;
+  std::vector<hipEvent_t> ev;
+  int used = 0;
+  int pending = -1;
+  struct Rec {
+    int cls;
+    double bytes;
+    int e0, e1;
+  };
+  std::vector<Rec> recs;
+};
+
+namespace {
+Profiler* g_prof = nullptr;
+}
+
+Profiler* profiler_for_call() {
+  if (!g_prof) return nullptr;
+  const bool take = (g_prof->calls++ % g_prof->sample_every) == 0;
+  return take ? g_prof : nullptr;
+}
+
+Profiler* profiler_for_launch() {
+  if (!g_prof) return nullptr;
+  const bool take = (g_prof->launches++ % g_prof->sample_every) == 0;
+  return take ? g_prof : nullptr;
+}
+
+void profiler_start(Profiler* p, hipStream_t s) {
+  p->pending = -1;
+  if (p->used + 2 > (int)p->ev.size()) return;
+  if (hipEventRecord(p->ev[p->used], s) != hipSuccess) return;
+  p->pending = p->used++;
+}
+
+void profiler_stop(Profiler* p, hipStream_t s, int cls, double bytes) {
+  if (p->pending < 0) return;
+  if (hipEventRecord(p->ev[p->used], s) != hipSuccess) return;
+  p->recs.push_back(Profiler::Rec{cls, bytes, p->pending, p->used});
+  p->used++;
+  p->pending = -1;
+}
+
+size_t vec_bytes(int L, int prec) { return ((size_t)1 << L) * (prec == KG_C128 ? 16 : 8); }
+
+size_t ws_fixed_bytes() {
+  return align_up(sizeof(KState), 256) + align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256) +
+         align_up(sizeof(cplx_d) * kMaxGroups * kMaxScal, 256);
+}
+
+Geo make_geo(int L, int prec, int tile_bits_override) {
+  Geo g;
+  memset(&g, 0, sizeof(g));
+  g.L = L;
+  g.D = 1u << L;
+  const int tb_max = 12;
+  int tb = L - 10;
+  if (tile_bits_override >= 6) tb = tile_bits_override;
+  if (tb > tb_max) tb = tb_max;
+  if (tb > L) tb = L;
+  if (tb < 6) tb = 6;
+  // amplitudes per thread (2^RB) grow with the tile until register pressure
+  // limits them; the rest of the tile is spread over up to 16 wavefronts
+  static const int rb_c64[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+  static const int rb_c128[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2};
+  g.TB = tb;
+  g.RB = (prec == KG_C128) ? rb_c128[tb] : rb_c64[tb];
+  g.WB = tb - 6 - g.RB;
+  g.small = (L < g.TB) ? 1 : 0;
+  g.ntiles = g.small ? 1u : (1u << (L - g.TB));
+  g.grid = (int)(g.ntiles < (uint32_t)kMaxGrid ? g.ntiles : (uint32_t)kMaxGrid);
+  return g;
+}
+
+int tile_override_from_env() {
+  const char* e = getenv("KG_TILE_BITS");
+  return e ? atoi(e) : 0;
+}
+
+}  // namespace kg
+
+using namespace kg;
+
+extern "C" {
+
+const char* kg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t kg_version(void) { return 1; }
+
+size_t kg_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
+  if (check_xxz(h) != KG_OK || check_krylov(k) != KG_OK || check_prec(prec) != KG_OK) return 0;
+  const size_t vb = vec_bytes(h->L, prec);
+  return ws_fixed_bytes() + align_up(vb * (size_t)(k->m - 1), 256) + align_up(vb, 256);
+}
+
+size_t kg_states_bytes(const kg_xxz* h, int32_t N, int32_t ckpt_every, int32_t prec) {
+  if (check_xxz(h) != KG_OK || check_prec(prec) != KG_OK) return 0;
+  if (N < 1 || ckpt_every < 0 || ckpt_every > N) {
+    fail(KG_EINVAL, "bad N=%d or ckpt_every=%d", N, ckpt_every);
+    return 0;
+  }
+  const size_t vb = vec_bytes(h->L, prec);
+  if (ckpt_every == 0) return vb * (size_t)N;
+  const int nseg = (N + ckpt_every - 1) / ckpt_every;
+  return vb * (size_t)(nseg - 1 + ckpt_every);
+}
+
+kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void* w, void* stream) {
+  KG_CHECK(check_xxz(h));
+  KG_CHECK(check_prec(prec));
+  if (!isfinite(u)) return fail(KG_EINVAL, "u must be finite");
+  KG_CHECK(check_vec(v, prec, "v"));
+  KG_CHECK(check_vec(w, prec, "w"));
+  if (overlap(v, w, vec_bytes(h->L, prec))) return fail(KG_EINVAL, "v and w overlap");
+  const Geo g = make_geo(h->L, prec, tile_override_from_env());
+  const HvArgs a = make_hv(h, nullptr, u);
+  Profiler* prof = profiler_for_launch();
+  if (prof) profiler_start(prof, (hipStream_t)stream);
+  KG_HIP(launch_hv(prec, a, g, v, w, (hipStream_t)stream), "xxz_apply");
+  if (prof) profiler_stop(prof, (hipStream_t)stream, kProfHv, 2.0 * vec_bytes(h->L, prec));
+  return ok();
+}
+
+kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, int32_t prec,
+                      const void* v_in, void* v_out, void* ws, size_t ws_bytes, int32_t* m_eff_dev,
+                      void* stream) {
+  KG_CHECK(check_xxz(h));
+  KG_CHECK(check_krylov(k));
+  KG_CHECK(check_prec(prec));
+  if (!isfinite(u) || !isfinite(t)) return fail(KG_EINVAL, "u and t must be finite");
+  KG_CHECK(check_vec(v_in, prec, "v_in"));
+  KG_CHECK(check_vec(v_out, prec, "v_out"));
+  if (v_in != v_out && overlap(v_in, v_out, vec_bytes(h->L, prec)))
+    return fail(KG_EINVAL, "v_in and v_out overlap without being equal");
+  if (m_eff_dev && (uintptr_t)m_eff_dev % 4) return fail(KG_EINVAL, "m_eff_dev misaligned");
+  Workspace W;
+  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W));
+  const hipStream_t s = (hipStream_t)stream;
+  KrylovCall c;
+  c.hv = make_hv(h, nullptr, u);
+  c.geo = make_geo(h->L, prec, tile_override_from_env());
+  c.prec = prec;
+  c.m = k->m;
+  c.reorth = k->reorth;
+  c.t = t;
+  c.tol = k->breakdown_tol > 0.0 ? k->breakdown_tol : default_tol(prec);
+  c.v_in = v_in;
+  c.v_out = v_out;
+  c.m_eff_out = m_eff_dev;
+  KG_HIP(launch_init(W.st, s), "krylov_expv init");
+  KG_HIP(launch_krylov(c, W, s), "krylov_expv");
+  return ok();
+}
+
+kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                        const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                        double* F_dev, double* beta_dev, void* states, int32_t ckpt_every, void* ws,
+                        size_t ws_bytes, void* stream) {
+  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
+  if (!F_dev || !beta_dev) return fail(KG_EINVAL, "F_dev and beta_dev are required");
+  Workspace W;
+  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W));
+  SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
+              make_geo(h->L, prec, tile_override_from_env()), W, (hipStream_t)stream};
+  const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
+  KG_HIP(launch_init(W.st, a.stream), "grape_forward init");
+  KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
+  return ok();
+}
+
+kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                         const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                         double* F_dev, double* beta_dev, double* grad_dev, void* states,
+                         int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
+                         void* stream) {
+  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
+  if (!beta_dev || !grad_dev) return fail(KG_EINVAL, "beta_dev and grad_dev are required");
+  if (states_valid != 0 && states_valid != 1) return fail(KG_EINVAL, "states_valid must be 0 or 1");
+  Workspace W;
+  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W));
+  SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
+              make_geo(h->L, prec, tile_override_from_env()), W, (hipStream_t)stream};
+  const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
+  KG_HIP(launch_init(W.st, a.stream), "grape_gradient init");
+  if (!states_valid) KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
+  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev));
+  return ok();
+}
+
+kg_status grape_ascent_update(double* u_dev, const double* grad_dev, int32_t N, double eta,
+                              void* stream) {
+  if (!u_dev || !grad_dev) return fail(KG_EINVAL, "u_dev and grad_dev are required");
+  if (N < 1) return fail(KG_EINVAL, "N must be >= 1");
+  if (!isfinite(eta)) return fail(KG_EINVAL, "eta must be finite");
+  KG_HIP(launch_ascent(u_dev, grad_dev, N, eta, (hipStream_t)stream), "grape_ascent_update");
+  return ok();
+}
+
+kg_status kg_profile_begin(int32_t sample_every, int32_t max_launches) {
+  if (g_prof) return fail(KG_EINVAL, "profiling is already active");
+  if (sample_every < 1 || max_launches < 1 || max_launches > (1 << 22))
+    return fail(KG_EINVAL, "sample_every >= 1 and 1 <= max_launches <= 2^22 required");
+  Profiler* p = new Profiler();
+  p->sample_every = sample_every;
+  p->ev.resize(2 * (size_t)max_launches);
+  for (auto& e : p->ev) {
+    const hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) {
+      for (auto& f : p->ev)
+        if (f) hipEventDestroy(f);
+      delete p;
+      return hip_fail(r, "kg_profile_begin");
+    }
+  }
+  g_prof = p;
+  return ok();
+}
+
+kg_status kg_profile_end(int64_t* launches, double* ms, double* bytes) {
+  if (!g_prof) return fail(KG_EINVAL, "profiling is not active");
+  Profiler* p = g_prof;
+  g_prof = nullptr;
+  kg_status st = KG_OK;
+  for (int c = 0; c < kProfN; ++c) {
+    if (launches) launches[c] = 0;
+    if (ms) ms[c] = 0.0;
+    if (bytes) bytes[c] = 0.0;
+  }
+  if (!p->recs.empty()) {
+    hipError_t r = hipEventSynchronize(p->ev[p->recs.back().e1]);
+    if (r != hipSuccess) st = hip_fail(r, "kg_profile_end");
+    for (const auto& rec : p->recs) {
+      float t = 0.0f;
+      if (st == KG_OK) {
+        r = hipEventElapsedTime(&t, p->ev[rec.e0], p->ev[rec.e1]);
+        if (r != hipSuccess) st = hip_fail(r, "kg_profile_end");
+      }
+      if (launches) launches[rec.cls] += 1;
+      if (ms) ms[rec.cls] += t;
+      if (bytes) bytes[rec.cls] += rec.bytes;
+    }
+  }
+  for (auto& e : p->ev) hipEventDestroy(e);
+  delete p;
+  return st == KG_OK ? ok() : st;
+}
+
+kg_status kg_debug_index_map(int32_t L, uint32_t s0, uint32_t count, int32_t* n_anti_dev,
+                             uint32_t* partner_mask_dev, void* stream) {
+  if (L < KG_MIN_L || L > KG_MAX_L) return fail(KG_EINVAL, "L=%d outside [%d, %d]", L, KG_MIN_L, KG_MAX_L);
+  if (!n_anti_dev || !partner_mask_dev) return fail(KG_EINVAL, "outputs are required");
+  if ((uint64_t)s0 + count > ((uint64_t)1 << L)) return fail(KG_EINVAL, "range exceeds 2^L");
+  if (count == 0) return ok();
+  KG_HIP(launch_index_map(L, s0, count, n_anti_dev, partner_mask_dev, (hipStream_t)stream),
+         "kg_debug_index_map");
+  return ok();
+}
+
+}  // extern "C"

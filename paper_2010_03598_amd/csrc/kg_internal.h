@@ -1,0 +1,115 @@
+// Internal interface between the C-ABI layer (kg_capi.cpp) and the HIP kernels
+// (kg_kernels.hip).  Not installed; the public interface is include/kgrape.h.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace kg {
+
+constexpr int kMaxM = 64;          // largest Krylov dimension
+constexpr int kMaxScal = kMaxM + 2;  // reduction scalars per pass (window + norm + spare)
+constexpr int kGroup = 64;         // blocks per first-level reduction group
+constexpr int kMaxGrid = 2048;     // largest grid of the reducing kernels
+constexpr int kMaxGroups = kMaxGrid / kGroup;
+
+struct cplx_d {                    // complex FP64 with a fixed layout
+  double re, im;
+};
+
+// Scalars of one Krylov call, resident in device memory.  offd[k] couples
+// v_{k-1} and v_k (offd[0] = 0); scale[k] = 1/||stored vector k||.
+struct KState {
+  double alpha[kMaxM];
+  double offd[kMaxM + 1];
+  double scale[kMaxM + 1];
+  cplx_d coef[kMaxM];     // projection coefficients of the current step (window order)
+  cplx_d dcomb[kMaxM];    // combination coefficients beta0 * c_j * scale_j
+  double beta0;
+  double normT;           // max_{i<=k}(|alpha_i| + offd_i)
+  int32_t m_eff;
+  int32_t done;           // basis complete (normal end, breakdown or zero input)
+  int32_t pad_[2];
+  // GRAPE scalars
+  cplx_d overlap;         // beta = <f|psi_N>
+  double fid;
+  double pad2_;
+  uint32_t counters[kMaxGroups + 2];
+};
+
+struct HvArgs {            // the Hamiltonian H0 + u Hc of one chain
+  int32_t L;
+  int32_t hc_kind;         // 0: S^x on one site, 1: sum of S^z
+  int32_t hc_bit;          // flipped bit of the S^x control (L - site)
+  int32_t sz_count;        // number of S^z control sites
+  uint32_t sz_mask;        // bits of the S^z control sites
+  int32_t pad_;
+  double half_J;           // J/2 (hopping amplitude)
+  double c_zz;             // J*Delta/4 (diagonal unit)
+  const double* u_ptr;     // control amplitude in device memory, or nullptr
+  double u_val;            // control amplitude used when u_ptr == nullptr
+};
+
+struct Geo {               // tiling of one state vector
+  int32_t L;
+  int32_t TB;              // tile = 2^TB amplitudes, staged in LDS
+  int32_t RB;              // 2^RB amplitudes per thread
+  int32_t WB;              // 2^WB wavefronts per block
+  uint32_t D;
+  uint32_t ntiles;
+  int32_t small;           // D < 2^TB: amplitudes past D are masked
+  int32_t grid;            // blocks of the tiled kernels
+};
+
+Geo make_geo(int L, int prec, int tile_bits_override);
+int stream_grid(uint32_t D);
+
+struct Workspace {         // carved from the caller's workspace
+  KState* st;
+  cplx_d* partials;        // [kMaxGrid][kMaxScal]
+  cplx_d* gpartials;       // [kMaxGroups][kMaxScal]
+  void* basis;             // m-1 vectors (stored Krylov vectors 1..m-1)
+  void* lam;               // one vector (costate)
+};
+
+size_t ws_fixed_bytes();
+size_t vec_bytes(int L, int prec);
+
+// ---- sampled kernel timing (kg_profile_begin / kg_profile_end)
+enum ProfClass { kProfPassA = 0, kProfPassB, kProfCombine, kProfBracket, kProfOverlap, kProfHv, kProfN };
+struct Profiler;
+// Non-null while profiling is active and the current Krylov call is sampled.
+Profiler* profiler_for_call();
+Profiler* profiler_for_launch();
+void profiler_start(Profiler* p, hipStream_t s);
+void profiler_stop(Profiler* p, hipStream_t s, int cls, double bytes);
+
+// ---- launchers (kg_kernels.hip); all enqueue on `s` and return hipSuccess or the launch error
+hipError_t launch_hv(int prec, const HvArgs& a, const Geo& g, const void* v, void* w, hipStream_t s);
+
+struct KrylovCall {
+  HvArgs hv;
+  Geo geo;
+  int prec;
+  int m;
+  int reorth;
+  double t;
+  double tol;
+  const void* v_in;
+  void* v_out;
+  int32_t* m_eff_out;      // nullable
+};
+hipError_t launch_krylov(const KrylovCall& c, const Workspace& ws, hipStream_t s);
+
+hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, const Workspace& ws,
+                          double* F_dev, double* beta_dev, hipStream_t s);
+hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
+                          double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
+                          hipStream_t s);
+hipError_t launch_init(KState* st, hipStream_t s);
+hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
+hipError_t launch_index_map(int L, uint32_t s0, uint32_t count, int32_t* n_anti, uint32_t* pmask,
+                            hipStream_t s);
+
+}  // namespace kg
