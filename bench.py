@@ -152,7 +152,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--profile-every", type=int, default=4,
+    ap.add_argument("--profile-every", type=int, default=64,
                     help="time every n-th Krylov call's kernels with HIP events (0: off)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -174,12 +174,19 @@ def main():
 
     sec64, F64, g64, prof = time_gradients(kg, torch, c, torch.complex64, ckpt, args.steps,
                                            args.warmup, args.profile_every)
-    sec128, F128, g128, _ = time_gradients(kg, torch, c, torch.complex128, ckpt, args.fp64_steps,
-                                           0, 0)
+    if args.fp64_steps > 0:
+        sec128, F128, g128, _ = time_gradients(kg, torch, c, torch.complex128, ckpt,
+                                               args.fp64_steps, 0, 0)
+    else:
+        sec128, F128, g128 = float("nan"), F64, g64
     errF = abs(F64 - F128) / abs(F128)
     errg = float(np.linalg.norm(g64 - g128) / np.linalg.norm(g128))
     errg_inf = float(np.abs(g64 - g128).max() / np.abs(g128).max())
 
+    if prof is None:
+        print(json.dumps({"metric": METRIC, "value": 1.0 / sec64, "unit": "gradient evals/s",
+                          "ms_per_step": sec64 * 1e3, "profile": "off"}), flush=True)
+        return
     # dominant kernel: the class with the largest sampled time
     dom = max(("pass_a", "pass_b", "combine", "bracket", "overlap"), key=lambda k: prof[k]["ms"])
     d = prof[dom]

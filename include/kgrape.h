@@ -101,17 +101,20 @@ const char* kg_last_error(void);
 int32_t kg_version(void);
 
 /* Bytes of workspace that krylov_expv, grape_forward and grape_gradient need
- * for this chain, Krylov dimension and precision: the m-1 Krylov basis
- * vectors, one costate vector, and a fixed block of scalars and reduction
- * partials.  Returns 0 for invalid arguments. */
+ * for this chain, Krylov dimension and precision: two Krylov slots (scalars,
+ * reduction partials and m-1 basis vectors each; the second one advances the
+ * segment recomputation beside the backward sweep) and one costate vector.
+ * Returns 0 for invalid arguments. */
 size_t kg_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec);
 
 /* Bytes of the forward-state buffer of grape_forward/grape_gradient.
  * ckpt_every = 0 stores psi_1..psi_N (N vectors).  ckpt_every = c in 1..N
- * stores psi_c, psi_2c, ... below the last segment (ceil(N/c)-1 vectors) plus
- * a segment buffer of c vectors, and recomputes each segment from its
- * checkpoint during the backward sweep (sqrt(N) checkpointing when c ~ sqrt(N)).
- * Returns 0 for invalid arguments. */
+ * splits the slices into segments (q c, (q+1) c]; it stores psi_c, psi_2c, ...
+ * below the last segment (ceil(N/c)-1 vectors) plus two segment buffers of c
+ * vectors (one if there is a single segment).  The backward sweep recomputes
+ * each earlier segment from its checkpoint beside the costate propagation of
+ * the later one (sqrt(N) checkpointing when c ~ sqrt(N)).  Returns 0 for
+ * invalid arguments. */
 size_t kg_states_bytes(const kg_xxz* h, int32_t N, int32_t ckpt_every, int32_t prec);
 
 /* w = (H0 + u Hc) v  (Eqs. 1, 6, 10; matrix-free).  v and w: D amplitudes of
@@ -159,6 +162,55 @@ kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double
  * (u unchanged when g = 0).  N >= 1.  Errors: KG_EINVAL, KG_EDEVICE. */
 kg_status grape_ascent_update(double* u_dev, const double* grad_dev, int32_t N, double eta,
                               void* stream);
+
+/* ---------------------------------------------------------------- batched form
+ * Many independent chains (different L, Delta, N, m) evaluated by one
+ * persistent launch: for every chain the forward sweep, the overlap, the
+ * backward sweep and the per-slice gradient of Eq. 5 (store-all), in
+ * complex64 vectors with FP64 scalars.  Each chain is served by its own team
+ * of workgroups [team_first, team_first + team_size); the teams of different
+ * chains must not overlap and every team must lie in [0, n_blocks).  The
+ * chain's data are addressed by element offsets into the packed arrays:
+ *   u_all[off_u .. off_u+N), grad_all[off_u .. off_u+N)        controls, gradient
+ *   psi0_all / target_all[off_vec .. off_vec+2^L)              complex64 states
+ *   states_all[off_states .. off_states+N*2^L)                 forward states
+ *   ws + off_ws (256-aligned), kg_batched_chain_ws_bytes(L, m, team_size) bytes
+ * Supported: 10 <= L <= 20 and team_size <= 64. */
+typedef struct kg_chain {
+  kg_xxz h;
+  int32_t N;
+  int32_t m;
+  int32_t reorth;
+  int32_t team_first;
+  int32_t team_size;
+  int32_t pad_;
+  double dt;
+  double breakdown_tol;  /* 0: 64 * 2^-23 */
+  int64_t off_u;
+  int64_t off_vec;
+  int64_t off_states;
+  int64_t off_ws;
+} kg_chain;
+
+/* Scratch bytes of one chain of the batched form. 0 for invalid arguments. */
+size_t kg_batched_chain_ws_bytes(int32_t L, int32_t m, int32_t team_size);
+
+/* F and dF/du for n_chains chains in one persistent launch.  chains_host holds
+ * the descriptors for validation on the host; chains_dev is the same array in
+ * device memory, read by the kernel (keep the two identical).  Array lengths:
+ * u_len doubles in u_all and grad_all, vec_len amplitudes in psi0_all and
+ * target_all, states_len amplitudes in states_all, ws_bytes in ws.  n_blocks
+ * is the size of the persistent grid (at most the number of compute units, so
+ * that every team is resident at once).  F_all[c] = |beta_c|^2, beta_all[2c],
+ * beta_all[2c+1] = beta_c.  *status_dev becomes nonzero if a team barrier
+ * timed out (the results are then invalid).  Errors: KG_EINVAL, KG_EWORKSPACE,
+ * KG_EDEVICE. */
+kg_status grape_gradient_batched(const kg_chain* chains_host, const kg_chain* chains_dev,
+                                 int32_t n_chains, int32_t n_blocks, const double* u_all,
+                                 int64_t u_len, const void* psi0_all, const void* target_all,
+                                 int64_t vec_len, void* states_all, int64_t states_len,
+                                 double* F_all, double* beta_all, double* grad_all, void* ws,
+                                 size_t ws_bytes, int32_t* status_dev, void* stream);
 
 /* ---------------------------------------------------------------- diagnostics
  * Integer index maps of H0 for s = s0 .. s0+count-1 (L <= 30):

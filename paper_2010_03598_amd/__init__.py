@@ -8,6 +8,7 @@ include/kgrape.h); this package is its Python binding.
 
 from ._lib import (KG_C64, KG_C128, KG_HC_SX, KG_HC_SZ, KgError, LIB_PATH,  # noqa: F401
                    load as load_library)
+from .autograd import GrapeFidelity, fidelity  # noqa: F401
 from .api import (XXZ, GrapeResult, Krylov, Workspace, debug_index_map, profile,  # noqa: F401
                   grape_ascent_update, grape_forward, grape_gradient, krylov_expv, new_states,
                   states_bytes, xxz_apply)
@@ -16,4 +17,5 @@ __all__ = [
     "XXZ", "Krylov", "Workspace", "GrapeResult", "xxz_apply", "krylov_expv", "grape_forward",
     "grape_gradient", "grape_ascent_update", "debug_index_map", "new_states", "states_bytes",
     "KG_C64", "KG_C128", "KG_HC_SX", "KG_HC_SZ", "KgError", "load_library", "LIB_PATH", "profile",
+    "GrapeFidelity", "fidelity",
 ]

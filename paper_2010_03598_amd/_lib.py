@@ -37,6 +37,15 @@ class KgKrylov(ctypes.Structure):
                 ("breakdown_tol", ctypes.c_double)]
 
 
+class KgChain(ctypes.Structure):
+    _fields_ = [("h", KgXxz), ("N", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("reorth", ctypes.c_int32), ("team_first", ctypes.c_int32),
+                ("team_size", ctypes.c_int32), ("pad_", ctypes.c_int32), ("dt", ctypes.c_double),
+                ("breakdown_tol", ctypes.c_double), ("off_u", ctypes.c_int64),
+                ("off_vec", ctypes.c_int64), ("off_states", ctypes.c_int64),
+                ("off_ws", ctypes.c_int64)]
+
+
 class KgError(RuntimeError):
     def __init__(self, fn: str, status: int, message: str):
         super().__init__(f"{fn} failed with status {status}: {message}")
@@ -65,6 +74,9 @@ SIGNATURES = {
     "grape_ascent_update": (_I32, [_P, _P, _I32, _D, _P]),
     "kg_debug_index_map": (_I32, [_I32, _U32, _U32, _P, _P, _P]),
     "kg_profile_begin": (_I32, [_I32, _I32]),
+    "kg_batched_chain_ws_bytes": (_SZ, [_I32, _I32, _I32]),
+    "grape_gradient_batched": (_I32, [_P, _P, _I32, _I32, _P, ctypes.c_int64, _P, _P, ctypes.c_int64,
+                                      _P, ctypes.c_int64, _P, _P, _P, _P, _SZ, _P, _P]),
     "kg_profile_end": (_I32, [_P, _P, _P]),
 }
 

@@ -1,0 +1,58 @@
+"""The GRAPE fidelity as a differentiable torch function of the controls.
+
+forward:  grape_forward (forward sweep of Algorithm 1 and the overlap of Eq. 2),
+          keeping the forward states in the layout of `ckpt_every`
+          (sqrt(N) checkpointing when ckpt_every ~ sqrt(N)).
+backward: the library's adjoint sweep (grape_gradient with the saved states):
+          costates lambda_j propagated backwards from the target, the earlier
+          segments recomputed from their checkpoints beside it, and the
+          zeroth-order gradient of Eq. 5 per slice.
+
+The backward returns the paper's zeroth-order gradient, not the exact
+derivative of the piecewise-constant propagation: the two differ by O(dt)
+relative, so torch.autograd.gradcheck does not apply; the gradient is checked
+against the oracle's zeroth-order gradient and, through finite differences of
+the forward, against the exact piecewise-constant gradient within O(dt).
+"""
+
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from .api import XXZ, Krylov, Workspace, grape_forward, grape_gradient
+
+
+class GrapeFidelity(torch.autograd.Function):
+    """F(u) = |<f| U_N(u_N) ... U_1(u_1) |psi0>|^2 with the adjoint gradient."""
+
+    @staticmethod
+    def forward(ctx, u: torch.Tensor, h: XXZ, dt: float, k: Krylov, psi0: torch.Tensor,
+                target: torch.Tensor, ckpt_every: int = 0,
+                workspace: Optional[Workspace] = None):
+        u = u.detach().contiguous()
+        ws = workspace if workspace is not None else Workspace(h, k, psi0.dtype, psi0.device)
+        r = grape_forward(h, u, dt, k, psi0, target, ckpt_every=ckpt_every, workspace=ws)
+        ctx.h, ctx.dt, ctx.k, ctx.ckpt_every = h, dt, k, ckpt_every
+        ctx.psi0, ctx.target, ctx.ws = psi0, target, ws
+        ctx.states, ctx.beta = r.states, r.beta
+        ctx.save_for_backward(u)
+        return r.F.clone()
+
+    @staticmethod
+    def backward(ctx, gF: torch.Tensor):
+        (u,) = ctx.saved_tensors
+        r = grape_gradient(ctx.h, u, ctx.dt, ctx.k, ctx.psi0, ctx.target,
+                           ckpt_every=ctx.ckpt_every, states=ctx.states, states_valid=True,
+                           beta=ctx.beta, workspace=ctx.ws)
+        grad_u = r.grad * gF.to(r.grad.dtype)
+        ctx.states = None
+        return grad_u, None, None, None, None, None, None, None
+
+
+def fidelity(u: torch.Tensor, h: XXZ, dt: float, k: Krylov, psi0: torch.Tensor,
+             target: torch.Tensor, ckpt_every: int = 0,
+             workspace: Optional[Workspace] = None) -> torch.Tensor:
+    """Differentiable fidelity; u is a float64 device tensor of N controls."""
+    return GrapeFidelity.apply(u, h, dt, k, psi0, target, ckpt_every, workspace)

@@ -13,7 +13,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "kg_internal.h"
@@ -127,51 +129,61 @@ HvArgs make_hv(const kg_xxz* h, const double* u_ptr, double u_val) {
   return a;
 }
 
+size_t slot_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
+  return ws_fixed_bytes() + align_up(vec_bytes(h->L, prec) * (size_t)(k->m - 1), 256);
+}
+
+// The workspace holds two Krylov slots (scalars, reduction partials and m-1
+// basis vectors each) and one costate vector.  Slot 0 serves single calls and
+// the backward sweep, slot 1 the segment recomputation advanced beside it.
 kg_status carve(void* ws, size_t ws_bytes, const kg_xxz* h, const kg_krylov* k, int32_t prec,
-                Workspace* out) {
+                Workspace* out0, Workspace* out1) {
   if (!ws) return fail(KG_EWORKSPACE, "workspace is NULL");
   if ((uintptr_t)ws % 256) return fail(KG_EWORKSPACE, "workspace is not 256-byte aligned");
   const size_t need = kg_workspace_bytes(h, k, prec);
   if (ws_bytes < need)
     return fail(KG_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
   char* p = static_cast<char*>(ws);
-  out->st = reinterpret_cast<KState*>(p);
-  p += align_up(sizeof(KState), 256);
-  out->partials = reinterpret_cast<cplx_d*>(p);
-  p += align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256);
-  out->gpartials = reinterpret_cast<cplx_d*>(p);
-  p += align_up(sizeof(cplx_d) * kMaxGroups * kMaxScal, 256);
-  const size_t vb = vec_bytes(h->L, prec);
-  out->basis = p;
-  p += align_up(vb * (size_t)(k->m > 1 ? k->m - 1 : 0), 256);
-  out->lam = p;
+  Workspace* outs[2] = {out0, out1};
+  for (int i = 0; i < 2; ++i) {
+    Workspace* o = outs[i];
+    char* q = p + (size_t)i * slot_bytes(h, k, prec);
+    if (!o) continue;
+    o->st = reinterpret_cast<KState*>(q);
+    q += align_up(sizeof(KState), 256);
+    o->partials = reinterpret_cast<cplx_d*>(q);
+    q += align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256);
+    o->basis = q;
+    o->lam = p + 2 * slot_bytes(h, k, prec);
+  }
   return KG_OK;
 }
 
-// Where the forward states live in the caller's state buffer.
+// Where the forward states live in the caller's state buffer.  With
+// checkpoints every c slices, segment q holds slices (q c, (q+1) c]; psi_{(q+1)c}
+// of every segment but the last is a checkpoint, the other states of segment q
+// go to segment buffer (q mod 2).  The forward sweep therefore leaves the last
+// two segments in the buffers, and during the backward sweep of segment q the
+// other buffer receives the recomputation of segment q-1.
 struct States {
-  int N = 0, c = 0, nseg = 1, clast = 0;
+  int N = 0, c = 0, nseg = 1, nbuf = 1;
   char* base = nullptr;
   size_t vb = 0;
   const void* psi0 = nullptr;
 
-  void* ckpt(int q) const { return base + (size_t)(q - 1) * vb; }           // psi_{q c}, q >= 1
-  void* buf(int i) const { return base + (size_t)(nseg - 1 + i) * vb; }    // segment slot i
-  // slot that receives psi_j (j >= 1) during the forward sweep
-  void* fwd(int j) const {
-    if (c == 0) return base + (size_t)(j - 1) * vb;
-    if (j > clast) return buf(j - clast - 1);
-    if (j % c == 0) return ckpt(j / c);
-    return buf(j % c - 1);
+  void* ckpt(int q) const { return base + (size_t)(q - 1) * vb; }  // psi_{q c}, 1 <= q < nseg
+  void* buf(int q, int i) const {
+    const int b = (nbuf == 2) ? (q & 1) : 0;
+    return base + (size_t)(nseg - 1 + b * c + i) * vb;
   }
-  const void* fwd_in(int j) const { return j == 0 ? psi0 : fwd(j); }
-  // slot of psi_j during the backward sweep of its segment (after recomputation)
-  const void* bwd(int j) const {
+  // slot of psi_j (j >= 1), in the forward sweep and after recomputation alike
+  void* at(int j) const {
     if (c == 0) return base + (size_t)(j - 1) * vb;
-    const int q = (j - 1) / c, cs = q * c, len = (N - cs < c) ? N - cs : c;
-    if (j < cs + len || q == nseg - 1) return buf(j - cs - 1);
-    return ckpt(q + 1);
+    const int q = (j - 1) / c;
+    if (j % c == 0 && q < nseg - 1) return ckpt(q + 1);
+    return buf(q, j - q * c - 1);
   }
+  const void* at0(int j) const { return j == 0 ? psi0 : at(j); }
 };
 
 States make_states(int N, int c, void* base, size_t vb, const void* psi0) {
@@ -183,7 +195,7 @@ States make_states(int N, int c, void* base, size_t vb, const void* psi0) {
   s.psi0 = psi0;
   if (c > 0) {
     s.nseg = (N + c - 1) / c;
-    s.clast = (s.nseg - 1) * c;
+    s.nbuf = s.nseg > 1 ? 2 : 1;
   }
   return s;
 }
@@ -198,7 +210,8 @@ struct SweepArgs {
   const void* psi0;
   const void* target;
   Geo geo;
-  Workspace ws;
+  Workspace ws;    // slot 0: single calls and the backward sweep
+  Workspace ws1;   // slot 1: recomputation beside the backward sweep
   hipStream_t stream;
 };
 
@@ -219,12 +232,12 @@ KrylovCall krylov_call(const SweepArgs& a, int j, double t, const void* in, void
 
 kg_status forward_sweep(const SweepArgs& a, const States& S, double* F_dev, double* beta_dev) {
   for (int j = 1; j <= a.N; ++j) {
-    const KrylovCall c = krylov_call(a, j, a.dt, S.fwd_in(j - 1), S.fwd(j));
+    const KrylovCall c = krylov_call(a, j, a.dt, S.at0(j - 1), S.at(j));
     KG_HIP(launch_krylov(c, a.ws, a.stream), "forward sweep");
   }
   Profiler* prof = profiler_for_launch();
   if (prof) profiler_start(prof, a.stream);
-  KG_HIP(launch_overlap(a.prec, a.geo.D, a.target, S.fwd(a.N), a.ws, F_dev, beta_dev, a.stream),
+  KG_HIP(launch_overlap(a.prec, a.geo.D, a.target, S.at(a.N), a.ws, F_dev, beta_dev, a.stream),
          "overlap");
   if (prof) profiler_stop(prof, a.stream, kProfOverlap, 2.0 * vec_bytes(a.h->L, a.prec));
   return KG_OK;
@@ -237,27 +250,38 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
   for (int q = S.nseg - 1; q >= 0; --q) {
     const int cs = (S.c == 0) ? 0 : q * S.c;
     const int len = (S.c == 0) ? a.N : ((a.N - cs < S.c) ? a.N - cs : S.c);
-    if (S.c > 0 && q < S.nseg - 1) {
-      // recompute psi_{cs+1} .. psi_{cs+len-1} from the checkpoint psi_cs
-      const void* in = (q == 0) ? a.psi0 : S.ckpt(q);
-      for (int i = 1; i < len; ++i) {
-        const KrylovCall c = krylov_call(a, cs + i, a.dt, in, S.buf(i - 1));
-        KG_HIP(launch_krylov(c, a.ws, a.stream), "segment recomputation");
-        in = S.buf(i - 1);
-      }
-    }
+    // segment q-1 is recomputed beside this segment's backward sweep unless the
+    // forward sweep left it in its buffer (the two last segments)
+    const int rq = q - 1;
+    const bool recompute = S.c > 0 && rq >= 0 && rq <= S.nseg - 3;
+    const void* re_in = recompute ? (rq == 0 ? a.psi0 : S.ckpt(rq)) : nullptr;
+    int re_i = 1;
     for (int j = cs + len; j > cs; --j) {
       Profiler* prof = profiler_for_launch();
       if (prof) profiler_start(prof, a.stream);
-      KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.bwd(j), a.dt, beta_dev, a.ws,
+      KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.at(j), a.dt, beta_dev, a.ws,
                             grad_dev + (j - 1), a.stream),
              "gradient bracket");
       if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * vec_bytes(a.h->L, a.prec));
       if (j > 1) {
-        const KrylovCall c = krylov_call(a, j, -a.dt, lam, a.ws.lam);
-        KG_HIP(launch_krylov(c, a.ws, a.stream), "backward sweep");
+        const KrylovCall cb = krylov_call(a, j, -a.dt, lam, a.ws.lam);
+        if (recompute && re_i <= S.c - 1) {
+          const int jr = rq * S.c + re_i;
+          const KrylovCall cr = krylov_call(a, jr, a.dt, re_in, S.at(jr));
+          KG_HIP(launch_krylov_pair(cb, a.ws, cr, a.ws1, a.stream), "backward sweep");
+          re_in = S.at(jr);
+          ++re_i;
+        } else {
+          KG_HIP(launch_krylov(cb, a.ws, a.stream), "backward sweep");
+        }
         lam = a.ws.lam;
       }
+    }
+    for (; recompute && re_i <= S.c - 1; ++re_i) {
+      const int jr = rq * S.c + re_i;
+      const KrylovCall cr = krylov_call(a, jr, a.dt, re_in, S.at(jr));
+      KG_HIP(launch_krylov(cr, a.ws1, a.stream), "segment recomputation");
+      re_in = S.at(jr);
     }
   }
   return KG_OK;
@@ -334,8 +358,7 @@ void profiler_stop(Profiler* p, hipStream_t s, int cls, double bytes) {
 size_t vec_bytes(int L, int prec) { return ((size_t)1 << L) * (prec == KG_C128 ? 16 : 8); }
 
 size_t ws_fixed_bytes() {
-  return align_up(sizeof(KState), 256) + align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256) +
-         align_up(sizeof(cplx_d) * kMaxGroups * kMaxScal, 256);
+  return align_up(sizeof(KState), 256) + align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256);
 }
 
 Geo make_geo(int L, int prec, int tile_bits_override) {
@@ -379,8 +402,7 @@ int32_t kg_version(void) { return 1; }
 
 size_t kg_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
   if (check_xxz(h) != KG_OK || check_krylov(k) != KG_OK || check_prec(prec) != KG_OK) return 0;
-  const size_t vb = vec_bytes(h->L, prec);
-  return ws_fixed_bytes() + align_up(vb * (size_t)(k->m - 1), 256) + align_up(vb, 256);
+  return 2 * slot_bytes(h, k, prec) + align_up(vec_bytes(h->L, prec), 256);
 }
 
 size_t kg_states_bytes(const kg_xxz* h, int32_t N, int32_t ckpt_every, int32_t prec) {
@@ -392,7 +414,8 @@ size_t kg_states_bytes(const kg_xxz* h, int32_t N, int32_t ckpt_every, int32_t p
   const size_t vb = vec_bytes(h->L, prec);
   if (ckpt_every == 0) return vb * (size_t)N;
   const int nseg = (N + ckpt_every - 1) / ckpt_every;
-  return vb * (size_t)(nseg - 1 + ckpt_every);
+  const int nbuf = nseg > 1 ? 2 : 1;
+  return vb * (size_t)(nseg - 1 + nbuf * ckpt_every);
 }
 
 kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void* w, void* stream) {
@@ -424,7 +447,7 @@ kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, i
     return fail(KG_EINVAL, "v_in and v_out overlap without being equal");
   if (m_eff_dev && (uintptr_t)m_eff_dev % 4) return fail(KG_EINVAL, "m_eff_dev misaligned");
   Workspace W;
-  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W));
+  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, nullptr));
   const hipStream_t s = (hipStream_t)stream;
   KrylovCall c;
   c.hv = make_hv(h, nullptr, u);
@@ -448,12 +471,13 @@ kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double 
                         size_t ws_bytes, void* stream) {
   KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
   if (!F_dev || !beta_dev) return fail(KG_EINVAL, "F_dev and beta_dev are required");
-  Workspace W;
-  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W));
+  Workspace W, W1;
+  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, &W1));
   SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
-              make_geo(h->L, prec, tile_override_from_env()), W, (hipStream_t)stream};
+              make_geo(h->L, prec, tile_override_from_env()), W, W1, (hipStream_t)stream};
   const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
   KG_HIP(launch_init(W.st, a.stream), "grape_forward init");
+  KG_HIP(launch_init(W1.st, a.stream), "grape_forward init");
   KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
   return ok();
 }
@@ -466,12 +490,13 @@ kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double
   KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
   if (!beta_dev || !grad_dev) return fail(KG_EINVAL, "beta_dev and grad_dev are required");
   if (states_valid != 0 && states_valid != 1) return fail(KG_EINVAL, "states_valid must be 0 or 1");
-  Workspace W;
-  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W));
+  Workspace W, W1;
+  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, &W1));
   SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
-              make_geo(h->L, prec, tile_override_from_env()), W, (hipStream_t)stream};
+              make_geo(h->L, prec, tile_override_from_env()), W, W1, (hipStream_t)stream};
   const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
   KG_HIP(launch_init(W.st, a.stream), "grape_gradient init");
+  KG_HIP(launch_init(W1.st, a.stream), "grape_gradient init");
   if (!states_valid) KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
   KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev));
   return ok();
@@ -483,6 +508,70 @@ kg_status grape_ascent_update(double* u_dev, const double* grad_dev, int32_t N, 
   if (N < 1) return fail(KG_EINVAL, "N must be >= 1");
   if (!isfinite(eta)) return fail(KG_EINVAL, "eta must be finite");
   KG_HIP(launch_ascent(u_dev, grad_dev, N, eta, (hipStream_t)stream), "grape_ascent_update");
+  return ok();
+}
+
+size_t kg_batched_chain_ws_bytes(int32_t L, int32_t m, int32_t team_size) {
+  if (L < 10 || L > 20 || m < 1 || m > KG_MAX_M || team_size < 1 || team_size > 64) return 0;
+  return batched_chain_ws_bytes(L, m, team_size);
+}
+
+kg_status grape_gradient_batched(const kg_chain* chains_host, const kg_chain* chains_dev,
+                                 int32_t n_chains, int32_t n_blocks, const double* u_all,
+                                 int64_t u_len, const void* psi0_all, const void* target_all,
+                                 int64_t vec_len, void* states_all, int64_t states_len,
+                                 double* F_all, double* beta_all, double* grad_all, void* ws,
+                                 size_t ws_bytes, int32_t* status_dev, void* stream) {
+  if (!chains_host || !chains_dev) return fail(KG_EINVAL, "chain descriptors are required");
+  if (n_chains < 1 || n_chains > 4096) return fail(KG_EINVAL, "n_chains=%d outside [1, 4096]", n_chains);
+  int dev = 0, ncu = 0;
+  KG_HIP(hipGetDevice(&dev), "grape_gradient_batched");
+  KG_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
+         "grape_gradient_batched");
+  if (n_blocks < 1 || n_blocks > ncu)
+    return fail(KG_EINVAL, "n_blocks=%d outside [1, %d compute units]", n_blocks, ncu);
+  if (!u_all || !grad_all || !F_all || !beta_all || !status_dev)
+    return fail(KG_EINVAL, "u_all, grad_all, F_all, beta_all and status_dev are required");
+  KG_CHECK(check_vec(psi0_all, KG_C64, "psi0_all"));
+  KG_CHECK(check_vec(target_all, KG_C64, "target_all"));
+  KG_CHECK(check_vec(states_all, KG_C64, "states_all"));
+  if (!ws || (uintptr_t)ws % 256) return fail(KG_EWORKSPACE, "workspace missing or not 256-byte aligned");
+  std::vector<int> owner(n_blocks, -1);
+  std::vector<std::pair<int64_t, int64_t>> wsr;
+  for (int i = 0; i < n_chains; ++i) {
+    const kg_chain& c = chains_host[i];
+    KG_CHECK(check_xxz(&c.h));
+    if (c.h.L < 10 || c.h.L > 20) return fail(KG_EINVAL, "chain %d: L=%d outside [10, 20]", i, c.h.L);
+    if (c.N < 1) return fail(KG_EINVAL, "chain %d: N=%d", i, c.N);
+    if (c.m < 1 || c.m > KG_MAX_M) return fail(KG_EINVAL, "chain %d: m=%d", i, c.m);
+    if (c.reorth != 0 && c.reorth != 1) return fail(KG_EINVAL, "chain %d: reorth", i);
+    if (!isfinite(c.dt) || !(c.breakdown_tol >= 0.0) || !isfinite(c.breakdown_tol))
+      return fail(KG_EINVAL, "chain %d: dt or breakdown_tol", i);
+    if (c.team_size < 1 || c.team_size > 64 || c.team_first < 0 || c.team_first + c.team_size > n_blocks)
+      return fail(KG_EINVAL, "chain %d: team [%d, %d) outside the grid of %d", i, c.team_first,
+                  c.team_first + c.team_size, n_blocks);
+    for (int b = c.team_first; b < c.team_first + c.team_size; ++b) {
+      if (owner[b] >= 0) return fail(KG_EINVAL, "chains %d and %d share workgroup %d", owner[b], i, b);
+      owner[b] = i;
+    }
+    const int64_t D = (int64_t)1 << c.h.L;
+    if (c.off_u < 0 || c.off_u + c.N > u_len) return fail(KG_EINVAL, "chain %d: off_u out of range", i);
+    if (c.off_vec < 0 || c.off_vec + D > vec_len)
+      return fail(KG_EINVAL, "chain %d: off_vec out of range", i);
+    if (c.off_states < 0 || c.off_states + (int64_t)c.N * D > states_len)
+      return fail(KG_EINVAL, "chain %d: off_states out of range", i);
+    const int64_t wb = (int64_t)batched_chain_ws_bytes(c.h.L, c.m, c.team_size);
+    if (c.off_ws < 0 || c.off_ws % 256 || (size_t)(c.off_ws + wb) > ws_bytes)
+      return fail(KG_EWORKSPACE, "chain %d: workspace range [%lld, %lld) invalid for %zu bytes", i,
+                  (long long)c.off_ws, (long long)(c.off_ws + wb), ws_bytes);
+    wsr.push_back({c.off_ws, c.off_ws + wb});
+  }
+  std::sort(wsr.begin(), wsr.end());
+  for (size_t i = 1; i < wsr.size(); ++i)
+    if (wsr[i].first < wsr[i - 1].second) return fail(KG_EWORKSPACE, "chain workspaces overlap");
+  KG_HIP(launch_batched(chains_dev, n_chains, n_blocks, u_all, psi0_all, target_all, states_all,
+                        F_all, beta_all, grad_all, ws, status_dev, (hipStream_t)stream),
+         "grape_gradient_batched");
   return ok();
 }
 

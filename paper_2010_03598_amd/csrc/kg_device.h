@@ -1,0 +1,448 @@
+// Device helpers shared by the HIP translation units of libkgrape: wavefront
+// and grid reductions, the tridiagonal exponential, and H v on a tile.
+// Internal; included only by kg_kernels.hip and kg_batched.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdint.h>
+
+#include "kg_internal.h"
+
+namespace kg {
+namespace {
+
+template <typename R>
+struct VT;
+template <>
+struct VT<float> {
+  using T = float2;
+};
+template <>
+struct VT<double> {
+  using T = double2;
+};
+
+// ---------------------------------------------------------------------- helpers
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ void st_agent_u32(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Make this wavefront's device-coherent stores complete before what follows.
+__device__ __forceinline__ void complete_stores() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Deterministic grid-wide sum of `ns` complex FP64 values.  Every block
+// passes its block totals in `tot` (LDS); `b` is the block's index among the
+// G blocks that reduce together.  Returns true in exactly one block, the last
+// to arrive, with the grid totals in `tot`.  The last block adds the partials
+// in a fixed order (lane l takes blocks l, l+64, ...; then a fixed butterfly).
+//
+// The partials travel only through device-scope (sc1) stores and loads, which
+// are coherent across the XCDs' L2 caches; the stores are waited for before
+// the arrival counter is incremented.  No device-wide fence is needed, so the
+// L2 caches are never written back or invalidated here.
+__device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* counter, uint32_t b,
+                            uint32_t G) {
+  __shared__ int last;
+  if (G == 1) return true;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (wv == 0) {
+    for (int j = lane; j < ns; j += 64) {
+      st_agent(&partials[(size_t)b * kMaxScal + j].re, tot[j].re);
+      st_agent(&partials[(size_t)b * kMaxScal + j].im, tot[j].im);
+    }
+    complete_stores();
+    uint32_t prev = 0;
+    if (lane == 0)
+      prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    prev = __shfl(prev, 0, 64);
+    if (lane == 0) last = (prev == G - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  if (threadIdx.x == 0) st_agent_u32(counter, 0u);
+  for (int j = wv; j < ns; j += nw) {
+    double re = 0.0, im = 0.0;
+    // lane l adds blocks l, l+64, l+128, ... in order; 8 blocks per round trip
+    for (uint32_t b0 = 0; b0 < G; b0 += 8 * 64) {
+      double pr[8], pi[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t blk = b0 + q * 64 + lane;
+        const cplx_d* p = &partials[(size_t)min(blk, G - 1) * kMaxScal + j];
+        pr[q] = ld_agent(&p->re);
+        pi[q] = ld_agent(&p->im);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const bool in = (b0 + q * 64 + lane) < G;
+        re += in ? pr[q] : 0.0;
+        im += in ? pi[q] : 0.0;
+      }
+    }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) tot[j] = cplx_d{re, im};
+  }
+  __syncthreads();
+  return true;
+}
+
+// Sum the per-wavefront accumulators wacc[w * kMaxScal + j] of a block in
+// wavefront order.
+__device__ void block_totals(const cplx_d* wacc, int ns, cplx_d* tot) {
+  const int nw = blockDim.x >> 6;
+  for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    for (int q = 0; q < nw; ++q) {
+      re += wacc[q * kMaxScal + j].re;
+      im += wacc[q * kMaxScal + j].im;
+    }
+    tot[j] = cplx_d{re, im};
+  }
+  __syncthreads();
+}
+
+// exp(-i t T) e_1 for the real symmetric tridiagonal T held row by row in the
+// lanes of one wavefront (lane i: diagonal a, couplings lo = T[i][i-1] and
+// hi = T[i][i+1]; rows past the dimension are zero).  Scaled Taylor series:
+// the step is split into nsub pieces with |t/nsub| ||T||_inf <= 1/2 and each
+// piece uses 16 terms (remainder below 2^-17/17! relative).
+__device__ void tri_exp_wave(double a, double lo, double hi, double t, double& cr, double& ci) {
+  const int lane = threadIdx.x & 63;
+  const double nrm = wave_max(fabs(a) + lo + hi);
+  int nsub = (int)ceil(fabs(t) * nrm * 2.0);
+  if (nsub < 1) nsub = 1;
+  const double tau = t / (double)nsub;
+  double yr = (lane == 0) ? 1.0 : 0.0, yi = 0.0;
+  for (int step = 0; step < nsub; ++step) {
+    double tr = yr, ti = yi, ar = yr, ai = yi;
+#pragma unroll 4
+    for (int p = 1; p <= 16; ++p) {
+      const double dr = __shfl_up(tr, 1, 64), di = __shfl_up(ti, 1, 64);
+      const double ur = __shfl_down(tr, 1, 64), ui = __shfl_down(ti, 1, 64);
+      const double zr = a * tr + lo * dr + hi * ur;
+      const double zi = a * ti + lo * di + hi * ui;
+      const double c = tau / (double)p;
+      tr = c * zi;
+      ti = -c * zr;
+      ar += tr;
+      ai += ti;
+    }
+    yr = ar;
+    yi = ai;
+  }
+  cr = yr;
+  ci = yi;
+}
+
+// ---------------------------------------------------------------------- H v on a tile
+
+template <typename R, int RB>
+struct Tile {
+  static constexpr int NR = 1 << RB;
+  R xr[NR], xi[NR];  // stored vector at the thread's amplitudes
+  R yr[NR], yi[NR];  // (H x) at the thread's amplitudes
+};
+
+__device__ __forceinline__ uint32_t tile_of(const Geo& g, uint32_t it, uint32_t b, uint32_t G) {
+  if (G >= 8 && (G & 7u) == 0 && (g.ntiles & 7u) == 0) {
+    const uint32_t per = G >> 3, xcd = b & 7u, j = b >> 3;
+    return xcd * (g.ntiles >> 3) + j + it * per;
+  }
+  return b + it * G;
+}
+
+// Partner vectors fetched per round trip for the bonds that leave the tile:
+// about 128 bytes of partner amplitudes per thread, at most 4 vectors.
+template <typename R, int RB>
+struct FarSlots {
+  static constexpr int units = 16 / ((1 << RB) * (int)(sizeof(R) / 4));
+  static constexpr int n = units > 4 ? 4 : (units < 1 ? 1 : units);
+};
+
+// Basis vectors fetched per round trip in the projection/update loops: about
+// 128 bytes of amplitudes per thread, at most 8 vectors.
+template <typename R, int RB>
+struct WinSlots {
+  static constexpr int units = 16 / ((1 << RB) * (int)(sizeof(R) / 4));
+  static constexpr int n = units > 8 ? 8 : (units < 1 ? 1 : units);
+};
+
+// Take the next far bond from `glb` (or none) for one slot of a round trip.
+template <typename R>
+__device__ __forceinline__ void next_far(uint32_t& glb, R hJ, uint32_t& flip, R& coef) {
+  if (glb) {
+    const int p = __builtin_ctz(glb);
+    glb &= glb - 1;
+    flip = 3u << p;
+    coef = hJ;
+  } else {
+    flip = 0u;   // reads the thread's own amplitude, weighted by zero
+    coef = (R)0;
+  }
+}
+
+// y = (H0 + u Hc) x on one tile (amplitudes base .. base + 2^TB - 1).  The
+// tile's amplitudes, the S^x partners and the first far partners are requested
+// in one round trip before anything waits; when `done_flag` is set (a finished
+// Krylov basis) the function returns false after issuing them, without
+// touching LDS, and the caller returns.
+template <typename R, int RB>
+__device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const Geo& g,
+                                        uint32_t tile, const typename VT<R>::T* __restrict__ x,
+                                        typename VT<R>::T* lds, double u,
+                                        const int32_t* done_flag) {
+  using V = typename VT<R>::T;
+  constexpr int NR = 1 << RB;
+  constexpr int NS = FarSlots<R, RB>::n;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w = uniform_u32(threadIdx.x >> 6);
+  const int L = g.L;
+  const int TB = g.TB;
+  const uint32_t base = tile << TB;
+  const uint32_t eb = lane | (w << (6 + RB));
+  const uint32_t sU = base | (w << (6 + RB));
+  const uint32_t bondmask = (1u << (L - 1)) - 1u;
+  const R hJ = (R)a.half_J;
+  const R cu = (R)(0.5 * u);
+
+  // bonds whose two bits are both wavefront or tile bits (p >= 6+RB): their
+  // predicate is the same for every slot of the wavefront
+  const int p0 = 6 + RB;
+  uint32_t act = (sU ^ (sU >> 1)) & bondmask;
+  act = (act >> p0) << p0;
+  const uint32_t lds_bonds = (TB - 1 > p0) ? (act & ((1u << (TB - 1)) - 1u)) : 0u;
+  uint32_t glb = g.small ? 0u : (act & ~lds_bonds);
+  const bool sx_glb = (a.hc_kind == 0) && (a.hc_bit >= TB);
+
+  // ---- round trip 1: own amplitudes, S^x partners, first far partners
+  V own[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const uint32_t s = base | eb | ((uint32_t)r << 6);
+    if (!g.small || s < g.D) {
+      own[r] = x[s];
+    } else {
+      own[r].x = (R)0;
+      own[r].y = (R)0;
+    }
+  }
+  uint32_t f[NS];
+  R cf[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    if (j == 0 && sx_glb) {
+      f[0] = 1u << a.hc_bit;
+      cf[0] = cu;
+    } else {
+      next_far<R>(glb, hJ, f[j], cf[j]);
+    }
+  }
+  V gq[NS][NR];
+  if (!g.small) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) gq[j][r] = x[(base | eb | ((uint32_t)r << 6)) ^ f[j]];
+    }
+  }
+  if (done_flag && *done_flag) return false;
+
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    lds[eb | ((uint32_t)r << 6)] = own[r];
+    T.xr[r] = own[r].x;
+    T.xi[r] = own[r].y;
+  }
+  __syncthreads();
+
+  const R czz = (R)a.c_zz;
+  const R uR = (R)u;
+
+  // diagonal: J Delta/4 (L-1-2 n_anti) (+ u sum_{i in A}(1/2 - b_i) for the S^z control)
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const uint32_t s = base | eb | ((uint32_t)r << 6);
+    const int n = __popc((s ^ (s >> 1)) & bondmask);
+    R d = czz * (R)(L - 1 - 2 * n);
+    if (a.hc_kind == 1) d += uR * ((R)(0.5 * a.sz_count) - (R)__popc(s & a.sz_mask));
+    T.yr[r] = d * T.xr[r];
+    T.yi[r] = d * T.xi[r];
+  }
+
+  // bonds between two lane bits (p = 0..4): partner in LDS, per-lane coefficient
+  const int pl = min(4, L - 2);
+  for (int p = 0; p <= pl; ++p) {
+    const R c = (((lane >> p) ^ (lane >> (p + 1))) & 1u) ? hJ : (R)0;
+    const uint32_t pe = eb ^ (3u << p);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const V q = lds[pe | ((uint32_t)r << 6)];
+      T.yr[r] += c * q.x;
+      T.yi[r] += c * q.y;
+    }
+  }
+
+  // bond p = 5 (lane bit 5 with bit 6): per-lane coefficient, loads issued together
+  if (L - 2 >= 5) {
+    const uint32_t flip = 3u << 5;
+    V q[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = eb | ((uint32_t)r << 6);
+      q[r] = (6 < TB) ? lds[e ^ flip] : x[(base | e) ^ flip];
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t s = base | eb | ((uint32_t)r << 6);
+      const R c = (((s >> 5) ^ (s >> 6)) & 1u) ? hJ : (R)0;
+      T.yr[r] += c * q[r].x;
+      T.yi[r] += c * q[r].y;
+    }
+  }
+
+  // bonds between two register bits (p = 6 .. 6+RB-2): compile-time predicates
+#pragma unroll
+  for (int q = 0; q + 1 < RB; ++q) {
+    if (6 + q <= L - 2) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (((r >> q) ^ (r >> (q + 1))) & 1) {
+          const int rp = r ^ (3 << q);
+          T.yr[r] += hJ * T.xr[rp];
+          T.yi[r] += hJ * T.xi[rp];
+        }
+      }
+    }
+  }
+
+  // bond p = 6+RB-1 between the top register bit and the next bit (a wavefront
+  // or tile bit): for a given wavefront, the active slots are the half whose top
+  // register bit differs from that bit
+  if constexpr (RB >= 1) {
+   if (6 + RB - 1 <= L - 2) {
+    constexpr int p = 6 + RB - 1;
+    constexpr int NH = (NR / 2 > 0) ? NR / 2 : 1;
+    const uint32_t flip = 3u << p;
+    const bool in_lds = (p + 1 < TB);
+    const uint32_t hi = (sU >> (p + 1)) & 1u;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      if ((uint32_t)half != hi) {
+        V q[NH];
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+          const int r = j | (half << (RB - 1));
+          const uint32_t e = eb | ((uint32_t)r << 6);
+          q[j] = in_lds ? lds[e ^ flip] : x[(base | e) ^ flip];
+        }
+#pragma unroll
+        for (int j = 0; j < NH; ++j) {
+          const int r = j | (half << (RB - 1));
+          T.yr[r] += hJ * q[j].x;
+          T.yi[r] += hJ * q[j].y;
+        }
+      }
+    }
+   }
+  }
+
+  // uniform bonds with the partner inside the tile: LDS
+  {
+    uint32_t lb = lds_bonds;
+    while (lb) {
+      const int p = __builtin_ctz(lb);
+      lb &= lb - 1;
+      const uint32_t flip = 3u << p;
+      V q[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) q[r] = lds[(eb | ((uint32_t)r << 6)) ^ flip];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        T.yr[r] += hJ * q[r].x;
+        T.yi[r] += hJ * q[r].y;
+      }
+    }
+  }
+
+  // far partners of round trip 1, then the remaining far bonds NS per round trip
+  if (!g.small) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        T.yr[r] += cf[j] * gq[j][r].x;
+        T.yi[r] += cf[j] * gq[j][r].y;
+      }
+    }
+    while (glb) {
+#pragma unroll
+      for (int j = 0; j < NS; ++j) next_far<R>(glb, hJ, f[j], cf[j]);
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) gq[j][r] = x[(base | eb | ((uint32_t)r << 6)) ^ f[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          T.yr[r] += cf[j] * gq[j][r].x;
+          T.yi[r] += cf[j] * gq[j][r].y;
+        }
+      }
+    }
+  }
+
+  // S^x control inside the tile: u/2 times the amplitude with that bit flipped
+  if (a.hc_kind == 0 && !sx_glb) {
+    const uint32_t flip = 1u << a.hc_bit;
+    V q[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) q[r] = lds[(eb | ((uint32_t)r << 6)) ^ flip];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T.yr[r] += cu * q[r].x;
+      T.yi[r] += cu * q[r].y;
+    }
+  }
+  return true;
+}
+
+__device__ __forceinline__ double control_value(const HvArgs& a) {
+  return a.u_ptr ? *a.u_ptr : a.u_val;
+}
+
+}  // namespace
+}  // namespace kg

@@ -10,9 +10,7 @@ namespace kg {
 
 constexpr int kMaxM = 64;          // largest Krylov dimension
 constexpr int kMaxScal = kMaxM + 2;  // reduction scalars per pass (window + norm + spare)
-constexpr int kGroup = 64;         // blocks per first-level reduction group
 constexpr int kMaxGrid = 2048;     // largest grid of the reducing kernels
-constexpr int kMaxGroups = kMaxGrid / kGroup;
 
 struct cplx_d {                    // complex FP64 with a fixed layout
   double re, im;
@@ -35,7 +33,8 @@ struct KState {
   cplx_d overlap;         // beta = <f|psi_N>
   double fid;
   double pad2_;
-  uint32_t counters[kMaxGroups + 2];
+  uint32_t counter;        // arrivals in the running grid reduction
+  uint32_t pad3_[3];
 };
 
 struct HvArgs {            // the Hamiltonian H0 + u Hc of one chain
@@ -68,7 +67,6 @@ int stream_grid(uint32_t D);
 struct Workspace {         // carved from the caller's workspace
   KState* st;
   cplx_d* partials;        // [kMaxGrid][kMaxScal]
-  cplx_d* gpartials;       // [kMaxGroups][kMaxScal]
   void* basis;             // m-1 vectors (stored Krylov vectors 1..m-1)
   void* lam;               // one vector (costate)
 };
@@ -101,6 +99,9 @@ struct KrylovCall {
   int32_t* m_eff_out;      // nullable
 };
 hipError_t launch_krylov(const KrylovCall& c, const Workspace& ws, hipStream_t s);
+// Two independent calls of the same L, m, reorth and precision in the same launches.
+hipError_t launch_krylov_pair(const KrylovCall& c0, const Workspace& w0, const KrylovCall& c1,
+                              const Workspace& w1, hipStream_t s);
 
 hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, const Workspace& ws,
                           double* F_dev, double* beta_dev, hipStream_t s);
@@ -109,6 +110,16 @@ hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam
                           hipStream_t s);
 hipError_t launch_init(KState* st, hipStream_t s);
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
+
+// batched persistent form (kg_batched.hip); kg_chain comes from kgrape.h
+}  // namespace kg
+struct kg_chain;
+namespace kg {
+size_t batched_chain_ws_bytes(int L, int m, int team);
+hipError_t launch_batched(const kg_chain* chains_dev, int n_chains, int n_blocks, const double* u_all,
+                          const void* psi0_all, const void* target_all, void* states_all,
+                          double* F_all, double* beta_all, double* grad_all, void* ws,
+                          int32_t* status, hipStream_t s);
 hipError_t launch_index_map(int L, uint32_t s0, uint32_t count, int32_t* n_anti, uint32_t* pmask,
                             hipStream_t s);
 

@@ -40,410 +40,13 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
+#include "kg_device.h"
 #include "kg_internal.h"
 
 namespace kg {
 namespace {
-
-template <typename R>
-struct VT;
-template <>
-struct VT<float> {
-  using T = float2;
-};
-template <>
-struct VT<double> {
-  using T = double2;
-};
-
-// ---------------------------------------------------------------------- helpers
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-
-__device__ __forceinline__ void st_agent_u32(uint32_t* p, uint32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Make this wavefront's device-coherent stores complete before what follows.
-__device__ __forceinline__ void complete_stores() {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-// Deterministic grid-wide sum of `ns` complex FP64 values.  Every block
-// passes its block totals in `tot` (LDS).  Returns true in exactly one block,
-// the last to arrive, with the grid totals in `tot`.  Partials are combined
-// in a fixed order: blocks of a group of kGroup, then groups.
-//
-// The partials travel only through device-scope (sc1) stores and loads, which
-// are coherent across the XCDs' L2 caches; a store is waited for before the
-// arrival counter is incremented.  No device-wide fence is needed, so the L2
-// caches are never written back or invalidated here.
-__device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, cplx_d* gpartials,
-                            uint32_t* counters) {
-  __shared__ int last;
-  const uint32_t b = blockIdx.x, G = gridDim.x;
-  if (G == 1) return true;
-  const uint32_t grp = b / kGroup, ngrp = (G + kGroup - 1) / kGroup;
-  const uint32_t gsize = min((uint32_t)kGroup, G - grp * kGroup);
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-
-  if (wv == 0) {
-    for (int j = lane; j < ns; j += 64) {
-      st_agent(&partials[(size_t)b * kMaxScal + j].re, tot[j].re);
-      st_agent(&partials[(size_t)b * kMaxScal + j].im, tot[j].im);
-    }
-    complete_stores();
-    uint32_t prev = 0;
-    if (lane == 0)
-      prev = __hip_atomic_fetch_add(&counters[grp], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    prev = __shfl(prev, 0, 64);
-    if (lane == 0) last = (prev == gsize - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  if (threadIdx.x == 0) st_agent_u32(&counters[grp], 0u);
-  for (int j = wv; j < ns; j += nw) {
-    double re = 0.0, im = 0.0;
-    if ((uint32_t)lane < gsize) {
-      const cplx_d* p = &partials[(size_t)(grp * kGroup + lane) * kMaxScal + j];
-      re = ld_agent(&p->re);
-      im = ld_agent(&p->im);
-    }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (ngrp == 1) {
-      if (lane == 0) tot[j] = cplx_d{re, im};
-    } else if (lane == 0) {
-      st_agent(&gpartials[(size_t)grp * kMaxScal + j].re, re);
-      st_agent(&gpartials[(size_t)grp * kMaxScal + j].im, im);
-    }
-  }
-  complete_stores();
-  __syncthreads();
-  if (ngrp == 1) return true;
-  if (wv == 0) {
-    uint32_t prev = 0;
-    if (lane == 0)
-      prev = __hip_atomic_fetch_add(&counters[kMaxGroups], 1u, __ATOMIC_RELAXED,
-                                    __HIP_MEMORY_SCOPE_AGENT);
-    prev = __shfl(prev, 0, 64);
-    if (lane == 0) last = (prev == ngrp - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  if (threadIdx.x == 0) st_agent_u32(&counters[kMaxGroups], 0u);
-  for (int j = wv; j < ns; j += nw) {
-    double re = 0.0, im = 0.0;
-    if ((uint32_t)lane < ngrp) {
-      const cplx_d* p = &gpartials[(size_t)lane * kMaxScal + j];
-      re = ld_agent(&p->re);
-      im = ld_agent(&p->im);
-    }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) tot[j] = cplx_d{re, im};
-  }
-  __syncthreads();
-  return true;
-}
-
-// Sum the per-wavefront accumulators wacc[w * kMaxScal + j] of a block in
-// wavefront order.
-__device__ void block_totals(const cplx_d* wacc, int ns, cplx_d* tot) {
-  const int nw = blockDim.x >> 6;
-  for (int j = threadIdx.x; j < ns; j += blockDim.x) {
-    double re = 0.0, im = 0.0;
-    for (int q = 0; q < nw; ++q) {
-      re += wacc[q * kMaxScal + j].re;
-      im += wacc[q * kMaxScal + j].im;
-    }
-    tot[j] = cplx_d{re, im};
-  }
-  __syncthreads();
-}
-
-// exp(-i t T) e_1 for the real symmetric tridiagonal T held row by row in the
-// lanes of one wavefront (lane i: diagonal a, couplings lo = T[i][i-1] and
-// hi = T[i][i+1]; rows past the dimension are zero).  Scaled Taylor series:
-// the step is split into nsub pieces with |t/nsub| ||T||_inf <= 1/2 and each
-// piece uses 16 terms (remainder below 2^-17/17! relative).
-__device__ void tri_exp_wave(double a, double lo, double hi, double t, double& cr, double& ci) {
-  const int lane = threadIdx.x & 63;
-  const double nrm = wave_max(fabs(a) + lo + hi);
-  int nsub = (int)ceil(fabs(t) * nrm * 2.0);
-  if (nsub < 1) nsub = 1;
-  const double tau = t / (double)nsub;
-  double yr = (lane == 0) ? 1.0 : 0.0, yi = 0.0;
-  for (int step = 0; step < nsub; ++step) {
-    double tr = yr, ti = yi, ar = yr, ai = yi;
-#pragma unroll 4
-    for (int p = 1; p <= 16; ++p) {
-      const double dr = __shfl_up(tr, 1, 64), di = __shfl_up(ti, 1, 64);
-      const double ur = __shfl_down(tr, 1, 64), ui = __shfl_down(ti, 1, 64);
-      const double zr = a * tr + lo * dr + hi * ur;
-      const double zi = a * ti + lo * di + hi * ui;
-      const double c = tau / (double)p;
-      tr = c * zi;
-      ti = -c * zr;
-      ar += tr;
-      ai += ti;
-    }
-    yr = ar;
-    yi = ai;
-  }
-  cr = yr;
-  ci = yi;
-}
-
-// ---------------------------------------------------------------------- H v on a tile
-
-template <typename R, int RB>
-struct Tile {
-  static constexpr int NR = 1 << RB;
-  R xr[NR], xi[NR];  // stored vector at the thread's amplitudes
-  R yr[NR], yi[NR];  // (H x) at the thread's amplitudes
-};
-
-__device__ __forceinline__ uint32_t tile_of(const Geo& g, uint32_t it) {
-  const uint32_t G = gridDim.x, b = blockIdx.x;
-  if (G >= 8 && (G & 7u) == 0 && (g.ntiles & 7u) == 0) {
-    const uint32_t per = G >> 3, xcd = b & 7u, j = b >> 3;
-    return xcd * (g.ntiles >> 3) + j + it * per;
-  }
-  return b + it * G;
-}
-
-template <typename R, int RB>
-__device__ __forceinline__ void hv_tile(Tile<R, RB>& T, const HvArgs& a, const Geo& g,
-                                        uint32_t tile, const typename VT<R>::T* __restrict__ x,
-                                        typename VT<R>::T* lds, double u) {
-  using V = typename VT<R>::T;
-  constexpr int NR = 1 << RB;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t w = uniform_u32(threadIdx.x >> 6);
-  const int L = g.L;
-  const int TB = g.TB;
-  const uint32_t base = tile << TB;
-  const uint32_t eb = lane | (w << (6 + RB));
-  const uint32_t sU = base | (w << (6 + RB));
-
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const uint32_t e = eb | ((uint32_t)r << 6);
-    const uint32_t s = base | e;
-    V val;
-    if (!g.small || s < g.D) {
-      val = x[s];
-    } else {
-      val.x = (R)0;
-      val.y = (R)0;
-    }
-    lds[e] = val;
-    T.xr[r] = val.x;
-    T.xi[r] = val.y;
-  }
-  __syncthreads();
-
-  const R hJ = (R)a.half_J;
-  const R czz = (R)a.c_zz;
-  const uint32_t bondmask = (1u << (L - 1)) - 1u;
-  const R uR = (R)u;
-
-  // diagonal: J Delta/4 (L-1-2 n_anti) (+ u sum_{i in A}(1/2 - b_i) for the S^z control)
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const uint32_t s = base | eb | ((uint32_t)r << 6);
-    const int n = __popc((s ^ (s >> 1)) & bondmask);
-    R d = czz * (R)(L - 1 - 2 * n);
-    if (a.hc_kind == 1) d += uR * ((R)(0.5 * a.sz_count) - (R)__popc(s & a.sz_mask));
-    T.yr[r] = d * T.xr[r];
-    T.yi[r] = d * T.xi[r];
-  }
-
-  // bonds between two lane bits (p = 0..4): partner in LDS, per-lane coefficient
-  const int pl = min(4, L - 2);
-  for (int p = 0; p <= pl; ++p) {
-    const R c = (((lane >> p) ^ (lane >> (p + 1))) & 1u) ? hJ : (R)0;
-    const uint32_t pe = eb ^ (3u << p);
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const V q = lds[pe | ((uint32_t)r << 6)];
-      T.yr[r] += c * q.x;
-      T.yi[r] += c * q.y;
-    }
-  }
-
-  // bond p = 5 (lane bit 5 with bit 6): per-lane coefficient, loads issued together
-  if (L - 2 >= 5) {
-    const uint32_t flip = 3u << 5;
-    V q[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const uint32_t e = eb | ((uint32_t)r << 6);
-      q[r] = (6 < TB) ? lds[e ^ flip] : x[(base | e) ^ flip];
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const uint32_t s = base | eb | ((uint32_t)r << 6);
-      const R c = (((s >> 5) ^ (s >> 6)) & 1u) ? hJ : (R)0;
-      T.yr[r] += c * q[r].x;
-      T.yi[r] += c * q[r].y;
-    }
-  }
-
-  // bonds between two register bits (p = 6 .. 6+RB-2): compile-time predicates
-#pragma unroll
-  for (int q = 0; q + 1 < RB; ++q) {
-    if (6 + q <= L - 2) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        if (((r >> q) ^ (r >> (q + 1))) & 1) {
-          const int rp = r ^ (3 << q);
-          T.yr[r] += hJ * T.xr[rp];
-          T.yi[r] += hJ * T.xi[rp];
-        }
-      }
-    }
-  }
-
-  // bond p = 6+RB-1 between the top register bit and the next bit (a wavefront
-  // or tile bit): for a given wavefront, the active slots are the half whose top
-  // register bit differs from that bit
-  if constexpr (RB >= 1) {
-   if (6 + RB - 1 <= L - 2) {
-    constexpr int p = 6 + RB - 1;
-    constexpr int NH = (NR / 2 > 0) ? NR / 2 : 1;
-    const uint32_t flip = 3u << p;
-    const bool in_lds = (p + 1 < TB);
-    const uint32_t hi = (sU >> (p + 1)) & 1u;
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-      if ((uint32_t)half != hi) {
-        V q[NH];
-#pragma unroll
-        for (int j = 0; j < NH; ++j) {
-          const int r = j | (half << (RB - 1));
-          const uint32_t e = eb | ((uint32_t)r << 6);
-          q[j] = in_lds ? lds[e ^ flip] : x[(base | e) ^ flip];
-        }
-#pragma unroll
-        for (int j = 0; j < NH; ++j) {
-          const int r = j | (half << (RB - 1));
-          T.yr[r] += hJ * q[j].x;
-          T.yi[r] += hJ * q[j].y;
-        }
-      }
-    }
-   }
-  }
-
-  // bonds whose two bits are both wavefront or tile bits (p >= 6+RB): the
-  // predicate is the same for every slot of the wavefront.  Partners inside the
-  // tile come from LDS, the others from global memory; two active bonds are
-  // loaded per round trip.
-  {
-    const int p0 = 6 + RB;
-    uint32_t act = (sU ^ (sU >> 1)) & bondmask;
-    act = (p0 >= 32) ? 0u : (act >> p0) << p0;
-    const uint32_t lds_bonds = (TB - 1 > p0) ? (act & ((1u << (TB - 1)) - 1u)) : 0u;
-    uint32_t glb_bonds = act & ~lds_bonds;
-    uint32_t lb = lds_bonds;
-    while (lb) {
-      const int p = __builtin_ctz(lb);
-      lb &= lb - 1;
-      const uint32_t flip = 3u << p;
-      V q[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) q[r] = lds[(eb | ((uint32_t)r << 6)) ^ flip];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        T.yr[r] += hJ * q[r].x;
-        T.yi[r] += hJ * q[r].y;
-      }
-    }
-    while (glb_bonds) {
-      const int p1 = __builtin_ctz(glb_bonds);
-      glb_bonds &= glb_bonds - 1;
-      const uint32_t f1 = 3u << p1;
-      if (glb_bonds) {
-        const int p2 = __builtin_ctz(glb_bonds);
-        glb_bonds &= glb_bonds - 1;
-        const uint32_t f2 = 3u << p2;
-        V q1[NR], q2[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const uint32_t s = base | eb | ((uint32_t)r << 6);
-          q1[r] = x[s ^ f1];
-          q2[r] = x[s ^ f2];
-        }
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          T.yr[r] += hJ * q1[r].x;
-          T.yi[r] += hJ * q1[r].y;
-          T.yr[r] += hJ * q2[r].x;
-          T.yi[r] += hJ * q2[r].y;
-        }
-      } else {
-        V q1[NR];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) q1[r] = x[(base | eb | ((uint32_t)r << 6)) ^ f1];
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          T.yr[r] += hJ * q1[r].x;
-          T.yi[r] += hJ * q1[r].y;
-        }
-      }
-    }
-  }
-
-  // S^x control on one site: u/2 times the amplitude with that bit flipped
-  if (a.hc_kind == 0) {
-    const R cu = (R)(0.5 * u);
-    const uint32_t flip = 1u << a.hc_bit;
-    V q[NR];
-    if (a.hc_bit < TB) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) q[r] = lds[(eb | ((uint32_t)r << 6)) ^ flip];
-    } else {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) q[r] = x[(base | eb | ((uint32_t)r << 6)) ^ flip];
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      T.yr[r] += cu * q[r].x;
-      T.yi[r] += cu * q[r].y;
-    }
-  }
-}
-
-__device__ __forceinline__ double control_value(const HvArgs& a) {
-  return a.u_ptr ? *a.u_ptr : a.u_val;
-}
 
 // ---------------------------------------------------------------------- xxz_apply
 
@@ -460,9 +63,9 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_hv(HvArgs a, Geo g, co
   const uint32_t iters = g.ntiles / gridDim.x;
   Tile<R, RB> T;
   for (uint32_t it = 0; it < iters; ++it) {
-    const uint32_t tile = tile_of(g, it);
+    const uint32_t tile = tile_of(g, it, blockIdx.x, gridDim.x);
     if (it) __syncthreads();
-    hv_tile<R, RB>(T, a, g, tile, v, lds, u);
+    hv_tile<R, RB>(T, a, g, tile, v, lds, u, nullptr);
     const uint32_t base = tile << g.TB;
 #pragma unroll
     for (int r = 0; r < (1 << RB); ++r) {
@@ -492,7 +95,14 @@ struct LzArgs {
   double tol;
   KState* st;
   cplx_d* partials;
-  cplx_d* gpartials;
+};
+
+constexpr int kMaxJobs = 2;
+
+// Independent Krylov calls of the same shape advanced by the same launches:
+// blocks [j*G, (j+1)*G) serve job j.
+struct LzBatch {
+  LzArgs job[kMaxJobs];
 };
 
 template <typename V>
@@ -527,10 +137,9 @@ __device__ void finish_basis(const LzArgs& a, int m_eff, double fresh_alpha, dou
 }
 
 template <typename R, int RB>
-__global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_a(LzArgs a) {
+__device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
-  if (a.k > 0 && a.st->done) return;
   extern __shared__ unsigned char smem_raw[];
   V* lds = reinterpret_cast<V*>(smem_raw);
   __shared__ cplx_d tot[kMaxScal];
@@ -545,48 +154,46 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_a(LzArgs a) {
 
   const double u = control_value(a.hv);
   const V* x = slot_ptr<V>(a, a.k);
-  const uint32_t iters = a.geo.ntiles / gridDim.x;
+  const uint32_t iters = a.geo.ntiles / G;
   Tile<R, RB> T;
   for (uint32_t it = 0; it < iters; ++it) {
-    const uint32_t tile = tile_of(a.geo, it);
+    const uint32_t tile = tile_of(a.geo, it, bl, G);
     if (it) __syncthreads();
-    hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u);
+    if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, a.k > 0 ? &a.st->done : nullptr)) return;
     const uint32_t base = tile << a.geo.TB;
-    // window vectors other than v_k, two per round trip
-    for (int i = a.i0; i < a.k; i += 2) {
-      const bool two = (i + 1 < a.k);
-      const V* v1 = slot_ptr<V>(a, i);
-      const V* v2 = slot_ptr<V>(a, two ? i + 1 : i);
-      V q1[NR], q2[NR];
+    // window vectors other than v_k, NW per round trip
+    constexpr int NW = WinSlots<R, RB>::n;
+    for (int i = a.i0; i < a.k; i += NW) {
+      V q[NW][NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const uint32_t s = base | eb | ((uint32_t)r << 6);
-        const bool ok = !a.geo.small || s < a.geo.D;
-        q1[r] = ok ? v1[s] : V{(R)0, (R)0};
-        q2[r] = (ok && two) ? v2[s] : V{(R)0, (R)0};
-      }
-      double s1r = 0.0, s1i = 0.0, s2r = 0.0, s2i = 0.0;
+      for (int j = 0; j < NW; ++j) {
+        if (i + j < a.k) {
+          const V* vj = slot_ptr<V>(a, i + j);
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const double yr = T.yr[r], yi = T.yi[r];
-        const double ar = q1[r].x, ai = q1[r].y, br = q2[r].x, bi = q2[r].y;
-        s1r += ar * yr + ai * yi;
-        s1i += ar * yi - ai * yr;
-        s2r += br * yr + bi * yi;
-        s2i += br * yi - bi * yr;
+          for (int r = 0; r < NR; ++r) {
+            const uint32_t s = base | eb | ((uint32_t)r << 6);
+            const bool ok = !a.geo.small || s < a.geo.D;
+            q[j][r] = ok ? vj[s] : V{(R)0, (R)0};
+          }
+        }
       }
-      s1r = wave_sum(s1r);
-      s1i = wave_sum(s1i);
-      if ((int)lane == i - a.i0) {
-        acc_re += s1r;
-        acc_im += s1i;
-      }
-      if (two) {
-        s2r = wave_sum(s2r);
-        s2i = wave_sum(s2i);
-        if ((int)lane == i + 1 - a.i0) {
-          acc_re += s2r;
-          acc_im += s2i;
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        if (i + j < a.k) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double yr = T.yr[r], yi = T.yi[r];
+            const double vr = q[j][r].x, vi = q[j][r].y;
+            sr += vr * yr + vi * yi;
+            si += vr * yi - vi * yr;
+          }
+          sr = wave_sum(sr);
+          si = wave_sum(si);
+          if ((int)lane == i + j - a.i0) {
+            acc_re += sr;
+            acc_im += si;
+          }
         }
       }
     }
@@ -620,7 +227,7 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_a(LzArgs a) {
   if (lane == 0) wacc[wv * kMaxScal + nwin] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, ns, tot);
-  if (!grid_reduce(tot, ns, a.partials, a.gpartials, a.st->counters)) return;
+  if (!grid_reduce(tot, ns, a.partials, &a.st->counter, bl, G)) return;
   if (threadIdx.x >= 64) return;
 
   // ---- scalar update on wavefront 0 of the last block
@@ -669,10 +276,19 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_a(LzArgs a) {
 }
 
 template <typename R, int RB>
-__global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzArgs a) {
+__global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_a(LzBatch B) {
+  const uint32_t G = B.job[0].geo.grid;
+  if (blockIdx.x < G) {
+    pass_a_body<R, RB>(B.job[0], blockIdx.x, G);
+  } else {
+    pass_a_body<R, RB>(B.job[1], blockIdx.x - G, G);
+  }
+}
+
+template <typename R, int RB>
+__device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
-  if (a.st->done) return;
   extern __shared__ unsigned char smem_raw[];
   V* lds = reinterpret_cast<V*>(smem_raw);
   __shared__ cplx_d tot[kMaxScal];
@@ -687,12 +303,12 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzArgs a) {
   const double u = control_value(a.hv);
   const V* x = slot_ptr<V>(a, a.k);
   V* out = reinterpret_cast<V*>(a.basis) + (size_t)a.k * a.geo.D;
-  const uint32_t iters = a.geo.ntiles / gridDim.x;
+  const uint32_t iters = a.geo.ntiles / G;
   Tile<R, RB> T;
   for (uint32_t it = 0; it < iters; ++it) {
-    const uint32_t tile = tile_of(a.geo, it);
+    const uint32_t tile = tile_of(a.geo, it, bl, G);
     if (it) __syncthreads();
-    hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u);
+    if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, &a.st->done)) return;
     const uint32_t base = tile << a.geo.TB;
     double zr[NR], zi[NR];
 #pragma unroll
@@ -700,28 +316,33 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzArgs a) {
       zr[r] = sk * (double)T.yr[r];
       zi[r] = sk * (double)T.yi[r];
     }
-    // window vectors other than v_k, two per round trip
-    for (int i = a.i0; i < a.k; i += 2) {
-      const bool two = (i + 1 < a.k);
-      const cplx_d c1 = st->coef[i - a.i0];
-      const cplx_d c2 = two ? st->coef[i + 1 - a.i0] : cplx_d{0.0, 0.0};
-      const V* v1 = slot_ptr<V>(a, i);
-      const V* v2 = slot_ptr<V>(a, two ? i + 1 : i);
-      V q1[NR], q2[NR];
+    // window vectors other than v_k, NW per round trip
+    constexpr int NW = WinSlots<R, RB>::n;
+    for (int i = a.i0; i < a.k; i += NW) {
+      V q[NW][NR];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const uint32_t s = base | eb | ((uint32_t)r << 6);
-        const bool ok = !a.geo.small || s < a.geo.D;
-        q1[r] = ok ? v1[s] : V{(R)0, (R)0};
-        q2[r] = (ok && two) ? v2[s] : V{(R)0, (R)0};
+      for (int j = 0; j < NW; ++j) {
+        if (i + j < a.k) {
+          const V* vj = slot_ptr<V>(a, i + j);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const uint32_t s = base | eb | ((uint32_t)r << 6);
+            const bool ok = !a.geo.small || s < a.geo.D;
+            q[j][r] = ok ? vj[s] : V{(R)0, (R)0};
+          }
+        }
       }
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const double ar = q1[r].x, ai = q1[r].y, br = q2[r].x, bi = q2[r].y;
-        zr[r] -= c1.re * ar - c1.im * ai;
-        zi[r] -= c1.re * ai + c1.im * ar;
-        zr[r] -= c2.re * br - c2.im * bi;
-        zi[r] -= c2.re * bi + c2.im * br;
+      for (int j = 0; j < NW; ++j) {
+        if (i + j < a.k) {
+          const cplx_d c = st->coef[i + j - a.i0];
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double vr = q[j][r].x, vi = q[j][r].y;
+            zr[r] -= c.re * vr - c.im * vi;
+            zi[r] -= c.re * vi + c.im * vr;
+          }
+        }
       }
     }
     {
@@ -752,7 +373,7 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzArgs a) {
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, 1, tot);
-  if (!grid_reduce(tot, 1, a.partials, a.gpartials, a.st->counters)) return;
+  if (!grid_reduce(tot, 1, a.partials, &a.st->counter, bl, G)) return;
   if (threadIdx.x >= 64) return;
 
   KState* stw = a.st;
@@ -766,44 +387,78 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzArgs a) {
   }
 }
 
+template <typename R, int RB>
+__global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzBatch B) {
+  const uint32_t G = B.job[0].geo.grid;
+  if (blockIdx.x < G) {
+    pass_b_body<R, RB>(B.job[0], blockIdx.x, G);
+  } else {
+    pass_b_body<R, RB>(B.job[1], blockIdx.x - G, G);
+  }
+}
+
 // ---------------------------------------------------------------------- streaming kernels
 
 constexpr int kStreamBlock = 256;
 constexpr int kStreamUnroll = 4;
 
+struct CombJob {
+  const KState* st;
+  const void* slot0;
+  const void* basis;
+  void* out;
+  int32_t* m_eff_out;
+};
+
+struct CombBatch {
+  CombJob job[kMaxJobs];
+  uint32_t D;
+  uint32_t grid;  // blocks per job
+};
+
 template <typename R>
-__global__ void __launch_bounds__(kStreamBlock)
-    k_combine(const KState* __restrict__ st, uint32_t D, const typename VT<R>::T* slot0,
-              const typename VT<R>::T* basis, typename VT<R>::T* out, int32_t* m_eff_out) {
+__device__ __forceinline__ void combine_body(const CombJob& cj, uint32_t D, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
+  constexpr int NJ = 4;  // basis vectors per round trip
+  const KState* __restrict__ st = cj.st;
+  const V* slot0 = reinterpret_cast<const V*>(cj.slot0);
+  const V* basis = reinterpret_cast<const V*>(cj.basis);
+  V* out = reinterpret_cast<V*>(cj.out);
   const int me = st->m_eff;
-  const uint32_t stride = gridDim.x * kStreamBlock;
-  for (uint32_t s0 = blockIdx.x * kStreamBlock + threadIdx.x; s0 < D; s0 += stride * kStreamUnroll) {
+  const uint32_t stride = G * kStreamBlock;
+  for (uint32_t s0 = bl * kStreamBlock + threadIdx.x; s0 < D; s0 += stride * kStreamUnroll) {
     double ar[kStreamUnroll], ai[kStreamUnroll];
 #pragma unroll
     for (int q = 0; q < kStreamUnroll; ++q) {
       ar[q] = 0.0;
       ai[q] = 0.0;
     }
-    for (int j = 0; j < me; ++j) {
-      const cplx_d c = st->dcomb[j];
-      const V* vj = (j == 0) ? slot0 : basis + (size_t)(j - 1) * D;
-      V v[kStreamUnroll];
+    for (int j0 = 0; j0 < me; j0 += NJ) {
+      V v[NJ][kStreamUnroll];
 #pragma unroll
-      for (int q = 0; q < kStreamUnroll; ++q) {
-        const uint32_t s = s0 + q * stride;
-        if (s < D) {
-          v[q] = vj[s];
-        } else {
-          v[q].x = (R)0;
-          v[q].y = (R)0;
+      for (int jj = 0; jj < NJ; ++jj) {
+        const int j = j0 + jj;
+        if (j < me) {
+          const V* vj = (j == 0) ? slot0 : basis + (size_t)(j - 1) * D;
+#pragma unroll
+          for (int q = 0; q < kStreamUnroll; ++q) {
+            const uint32_t s = s0 + q * stride;
+            v[jj][q] = (s < D) ? vj[s] : V{(R)0, (R)0};
+          }
         }
       }
 #pragma unroll
-      for (int q = 0; q < kStreamUnroll; ++q) {
-        const double vr = v[q].x, vi = v[q].y;
-        ar[q] += c.re * vr - c.im * vi;
-        ai[q] += c.re * vi + c.im * vr;
+      for (int jj = 0; jj < NJ; ++jj) {
+        const int j = j0 + jj;
+        if (j < me) {
+          const cplx_d c = st->dcomb[j];
+#pragma unroll
+          for (int q = 0; q < kStreamUnroll; ++q) {
+            const double vr = v[jj][q].x, vi = v[jj][q].y;
+            ar[q] += c.re * vr - c.im * vi;
+            ai[q] += c.re * vi + c.im * vr;
+          }
+        }
       }
     }
 #pragma unroll
@@ -817,30 +472,58 @@ __global__ void __launch_bounds__(kStreamBlock)
       }
     }
   }
-  if (m_eff_out && blockIdx.x == 0 && threadIdx.x == 0) *m_eff_out = me;
+  if (cj.m_eff_out && bl == 0 && threadIdx.x == 0) *cj.m_eff_out = me;
 }
+
+template <typename R>
+__global__ void __launch_bounds__(kStreamBlock) k_combine(CombBatch B) {
+  if (blockIdx.x < B.grid) {
+    combine_body<R>(B.job[0], B.D, blockIdx.x, B.grid);
+  } else {
+    combine_body<R>(B.job[1], B.D, blockIdx.x - B.grid, B.grid);
+  }
+}
+
+// Elements per thread and round trip of the reducing streaming kernels.
+template <typename R>
+struct RedChunk {
+  static constexpr int n = (sizeof(R) == 4) ? 16 : 8;
+};
 
 // beta = <f|psi> (Eq. 2); the last block writes beta, F = |beta|^2.
 template <typename R>
 __global__ void __launch_bounds__(kStreamBlock)
     k_overlap(uint32_t D, const typename VT<R>::T* __restrict__ f, const typename VT<R>::T* __restrict__ psi,
-              KState* st, cplx_d* partials, cplx_d* gpartials, double* F_dev, double* beta_dev) {
+              KState* st, cplx_d* partials, double* F_dev, double* beta_dev) {
+  using V = typename VT<R>::T;
+  constexpr int E = RedChunk<R>::n;
   __shared__ cplx_d wacc[(kStreamBlock / 64) * kMaxScal];
   __shared__ cplx_d tot[kMaxScal];
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const uint32_t T = gridDim.x * kStreamBlock;
+  const uint32_t tid = blockIdx.x * kStreamBlock + threadIdx.x;
   double sr = 0.0, si = 0.0;
-  const uint32_t stride = gridDim.x * kStreamBlock;
-  for (uint32_t s = blockIdx.x * kStreamBlock + threadIdx.x; s < D; s += stride) {
-    const double fr = f[s].x, fi = f[s].y, pr = psi[s].x, pi = psi[s].y;
-    sr += fr * pr + fi * pi;
-    si += fr * pi - fi * pr;
+  for (uint32_t base = 0; base < D; base += T * E) {
+    V a[E], b[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t s = base + e * T + tid;
+      a[e] = (s < D) ? f[s] : V{(R)0, (R)0};
+      b[e] = (s < D) ? psi[s] : V{(R)0, (R)0};
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double fr = a[e].x, fi = a[e].y, pr = b[e].x, pi = b[e].y;
+      sr += fr * pr + fi * pi;
+      si += fr * pi - fi * pr;
+    }
   }
   sr = wave_sum(sr);
   si = wave_sum(si);
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{sr, si};
   __syncthreads();
   block_totals(wacc, 1, tot);
-  if (!grid_reduce(tot, 1, partials, gpartials, st->counters)) return;
+  if (!grid_reduce(tot, 1, partials, &st->counter, blockIdx.x, gridDim.x)) return;
   if (threadIdx.x == 0) {
     const cplx_d b = tot[0];
     st->overlap = b;
@@ -858,33 +541,41 @@ template <typename R>
 __global__ void __launch_bounds__(kStreamBlock)
     k_bracket(HvArgs a, uint32_t D, const typename VT<R>::T* __restrict__ lam,
               const typename VT<R>::T* __restrict__ psi, double dt, const double* beta_dev,
-              KState* st, cplx_d* partials, cplx_d* gpartials, double* grad_slot) {
+              KState* st, cplx_d* partials, double* grad_slot) {
+  using V = typename VT<R>::T;
+  constexpr int E = RedChunk<R>::n;
   __shared__ cplx_d wacc[(kStreamBlock / 64) * kMaxScal];
   __shared__ cplx_d tot[kMaxScal];
   const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-  double sr = 0.0, si = 0.0;
-  const uint32_t stride = gridDim.x * kStreamBlock;
+  const uint32_t T = gridDim.x * kStreamBlock;
+  const uint32_t tid = blockIdx.x * kStreamBlock + threadIdx.x;
   const uint32_t flip = (a.hc_kind == 0) ? (1u << a.hc_bit) : 0u;
-  for (uint32_t s = blockIdx.x * kStreamBlock + threadIdx.x; s < D; s += stride) {
-    double pr, pi;
-    if (a.hc_kind == 0) {
-      pr = 0.5 * (double)psi[s ^ flip].x;
-      pi = 0.5 * (double)psi[s ^ flip].y;
-    } else {
-      const double dz = 0.5 * a.sz_count - (double)__popc(s & a.sz_mask);
-      pr = dz * (double)psi[s].x;
-      pi = dz * (double)psi[s].y;
+  double sr = 0.0, si = 0.0;
+  for (uint32_t base = 0; base < D; base += T * E) {
+    V l[E], p[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t s = base + e * T + tid;
+      l[e] = (s < D) ? lam[s] : V{(R)0, (R)0};
+      p[e] = (s < D) ? psi[s ^ flip] : V{(R)0, (R)0};
     }
-    const double lr = lam[s].x, li = lam[s].y;
-    sr += lr * pr + li * pi;
-    si += lr * pi - li * pr;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t s = base + e * T + tid;
+      // (Hc psi)[s]: S^x flips one bit with amplitude 1/2; sum of S^z is diagonal
+      const double hc = (a.hc_kind == 0) ? 0.5 : 0.5 * a.sz_count - (double)__popc(s & a.sz_mask);
+      const double pr = hc * (double)p[e].x, pi = hc * (double)p[e].y;
+      const double lr = l[e].x, li = l[e].y;
+      sr += lr * pr + li * pi;
+      si += lr * pi - li * pr;
+    }
   }
   sr = wave_sum(sr);
   si = wave_sum(si);
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{sr, si};
   __syncthreads();
   block_totals(wacc, 1, tot);
-  if (!grid_reduce(tot, 1, partials, gpartials, st->counters)) return;
+  if (!grid_reduce(tot, 1, partials, &st->counter, blockIdx.x, gridDim.x)) return;
   if (threadIdx.x == 0) {
     const double br = beta_dev[0], bi = beta_dev[1];
     const cplx_d B = tot[0];
@@ -918,8 +609,8 @@ __global__ void k_index_map(int L, uint32_t s0, uint32_t count, int32_t* n_anti,
 
 __global__ void k_init_state(KState* st) {
   const int i = threadIdx.x;
-  if (i < kMaxGroups + 2) st->counters[i] = 0u;
   if (i == 0) {
+    st->counter = 0u;
     st->done = 0;
     st->m_eff = 0;
     st->normT = 0.0;
@@ -954,68 +645,80 @@ hipError_t launch_hv_r(const HvArgs& a, const Geo& g, const void* v, void* w, hi
 }
 
 template <typename R, int RB>
-hipError_t launch_pass(bool pass_a, const LzArgs& la, hipStream_t s) {
-  const Geo& g = la.geo;
+hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s) {
+  const Geo& g = lb.job[0].geo;
+  const dim3 grid(g.grid * njobs), block(64 << g.WB);
   if (pass_a) {
-    hipLaunchKernelGGL((k_pass_a<R, RB>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, la);
+    hipLaunchKernelGGL((k_pass_a<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
   } else {
-    hipLaunchKernelGGL((k_pass_b<R, RB>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, la);
+    hipLaunchKernelGGL((k_pass_b<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
   }
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_pass_r(bool pass_a, const LzArgs& la, hipStream_t s) {
-  switch (la.geo.RB) {
-    case 0: return launch_pass<R, 0>(pass_a, la, s);
-    case 1: return launch_pass<R, 1>(pass_a, la, s);
-    case 2: return launch_pass<R, 2>(pass_a, la, s);
-    default: return launch_pass<R, 3>(pass_a, la, s);
+hipError_t launch_pass_r(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s) {
+  switch (lb.job[0].geo.RB) {
+    case 0: return launch_pass<R, 0>(pass_a, lb, njobs, s);
+    case 1: return launch_pass<R, 1>(pass_a, lb, njobs, s);
+    case 2: return launch_pass<R, 2>(pass_a, lb, njobs, s);
+    default: return launch_pass<R, 3>(pass_a, lb, njobs, s);
   }
 }
 
+// Advance n (1 or 2) independent Krylov calls of one shape (same L, m,
+// reorth, precision) through the same launches.
 template <typename R>
-hipError_t launch_krylov_t(const KrylovCall& c, const Workspace& ws, hipStream_t s) {
+hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss, int n, hipStream_t s) {
   using V = typename VT<R>::T;
-  LzArgs la;
-  la.hv = c.hv;
-  la.geo = c.geo;
-  la.slot0 = c.v_in;
-  la.basis = ws.basis;
-  la.m = c.m;
-  la.pad_ = 0;
-  la.t = c.t;
-  la.tol = c.tol;
-  la.st = ws.st;
-  la.partials = ws.partials;
-  la.gpartials = ws.gpartials;
+  const KrylovCall& c0 = calls[0];
+  LzBatch lb;
+  CombBatch cb;
+  memset(&lb, 0, sizeof(lb));
+  memset(&cb, 0, sizeof(cb));
+  for (int j = 0; j < n; ++j) {
+    LzArgs& la = lb.job[j];
+    la.hv = calls[j].hv;
+    la.geo = calls[j].geo;
+    la.slot0 = calls[j].v_in;
+    la.basis = wss[j]->basis;
+    la.m = calls[j].m;
+    la.t = calls[j].t;
+    la.tol = calls[j].tol;
+    la.st = wss[j]->st;
+    la.partials = wss[j]->partials;
+    cb.job[j] = CombJob{wss[j]->st, calls[j].v_in, wss[j]->basis, calls[j].v_out, calls[j].m_eff_out};
+  }
   Profiler* prof = profiler_for_call();
-  const double vb = (double)c.geo.D * sizeof(V);
+  const double vb = (double)c0.geo.D * sizeof(V) * n;
   hipError_t e;
-  for (int k = 0; k < c.m; ++k) {
-    const bool last = (k == c.m - 1);
-    la.k = k;
-    la.i0 = last ? k : (c.reorth ? 0 : (k > 0 ? k - 1 : 0));
-    const int nwin = k - la.i0 + 1;
+  for (int k = 0; k < c0.m; ++k) {
+    const bool last = (k == c0.m - 1);
+    const int i0 = last ? k : (c0.reorth ? 0 : (k > 0 ? k - 1 : 0));
+    for (int j = 0; j < n; ++j) {
+      lb.job[j].k = k;
+      lb.job[j].i0 = i0;
+    }
+    const int nwin = k - i0 + 1;
     if (prof) profiler_start(prof, s);
-    if ((e = launch_pass_r<R>(true, la, s)) != hipSuccess) return e;
+    if ((e = launch_pass_r<R>(true, lb, n, s)) != hipSuccess) return e;
     // algorithmic bytes: the window vectors (v_k included) are read once
     if (prof) profiler_stop(prof, s, kProfPassA, nwin * vb);
     if (!last) {
       if (prof) profiler_start(prof, s);
-      if ((e = launch_pass_r<R>(false, la, s)) != hipSuccess) return e;
+      if ((e = launch_pass_r<R>(false, lb, n, s)) != hipSuccess) return e;
       // the window vectors are read and v_{k+1} is written
       if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 1) * vb);
     }
   }
-  const uint32_t D = c.geo.D;
+  const uint32_t D = c0.geo.D;
+  cb.D = D;
+  cb.grid = (uint32_t)stream_grid(D);
   if (prof) profiler_start(prof, s);
-  hipLaunchKernelGGL((k_combine<R>), dim3(stream_grid(D)), dim3(kStreamBlock), 0, s,
-                     (const KState*)ws.st, D, reinterpret_cast<const V*>(c.v_in),
-                     reinterpret_cast<const V*>(ws.basis), reinterpret_cast<V*>(c.v_out), c.m_eff_out);
+  hipLaunchKernelGGL((k_combine<R>), dim3(cb.grid * n), dim3(kStreamBlock), 0, s, cb);
   e = hipGetLastError();
   // m basis vectors read (fewer after a breakdown), v_out written
-  if (prof) profiler_stop(prof, s, kProfCombine, (c.m + 1) * vb);
+  if (prof) profiler_stop(prof, s, kProfCombine, (c0.m + 1) * vb);
   return e;
 }
 
@@ -1041,20 +744,36 @@ hipError_t launch_hv(int prec, const HvArgs& a, const Geo& g, const void* v, voi
 }
 
 hipError_t launch_krylov(const KrylovCall& c, const Workspace& ws, hipStream_t s) {
-  return c.prec == 0 ? launch_krylov_t<double>(c, ws, s) : launch_krylov_t<float>(c, ws, s);
+  const Workspace* w[1] = {&ws};
+  return c.prec == 0 ? launch_krylov_t<double>(&c, w, 1, s) : launch_krylov_t<float>(&c, w, 1, s);
+}
+
+hipError_t launch_krylov_pair(const KrylovCall& c0, const Workspace& w0, const KrylovCall& c1,
+                              const Workspace& w1, hipStream_t s) {
+  const KrylovCall c[2] = {c0, c1};
+  const Workspace* w[2] = {&w0, &w1};
+  return c0.prec == 0 ? launch_krylov_t<double>(c, w, 2, s) : launch_krylov_t<float>(c, w, 2, s);
+}
+
+int reduce_grid(uint32_t D, int prec) {
+  const uint64_t per = (uint64_t)kStreamBlock * (prec == 0 ? RedChunk<double>::n : RedChunk<float>::n);
+  uint64_t g = (D + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > 256) g = 256;
+  return (int)g;
 }
 
 hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, const Workspace& ws,
                           double* F_dev, double* beta_dev, hipStream_t s) {
-  const int grid = stream_grid(D);
+  const int grid = reduce_grid(D, prec);
   if (prec == 0) {
     hipLaunchKernelGGL(k_overlap<double>, dim3(grid), dim3(kStreamBlock), 0, s, D,
                        reinterpret_cast<const double2*>(f), reinterpret_cast<const double2*>(psi),
-                       ws.st, ws.partials, ws.gpartials, F_dev, beta_dev);
+                       ws.st, ws.partials, F_dev, beta_dev);
   } else {
     hipLaunchKernelGGL(k_overlap<float>, dim3(grid), dim3(kStreamBlock), 0, s, D,
                        reinterpret_cast<const float2*>(f), reinterpret_cast<const float2*>(psi),
-                       ws.st, ws.partials, ws.gpartials, F_dev, beta_dev);
+                       ws.st, ws.partials, F_dev, beta_dev);
   }
   return hipGetLastError();
 }
@@ -1062,15 +781,15 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
 hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
                           double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
                           hipStream_t s) {
-  const int grid = stream_grid(D);
+  const int grid = reduce_grid(D, prec);
   if (prec == 0) {
     hipLaunchKernelGGL(k_bracket<double>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const double2*>(lam), reinterpret_cast<const double2*>(psi),
-                       dt, beta_dev, ws.st, ws.partials, ws.gpartials, grad_slot);
+                       dt, beta_dev, ws.st, ws.partials, grad_slot);
   } else {
     hipLaunchKernelGGL(k_bracket<float>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const float2*>(lam), reinterpret_cast<const float2*>(psi),
-                       dt, beta_dev, ws.st, ws.partials, ws.gpartials, grad_slot);
+                       dt, beta_dev, ws.st, ws.partials, grad_slot);
   }
   return hipGetLastError();
 }

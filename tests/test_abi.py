@@ -56,11 +56,12 @@ def test_workspace_and_state_sizes(lib):
     ws128 = lib.kg_workspace_bytes(ctypes.byref(h), ctypes.byref(k), _lib.KG_C128)
     ws64 = lib.kg_workspace_bytes(ctypes.byref(h), ctypes.byref(k), _lib.KG_C64)
     vb128, vb64 = 16 << 10, 8 << 10
-    assert ws128 - ws64 == 8 * (vb128 - vb64)          # 7 basis vectors + 1 costate
+    assert ws128 - ws64 == 15 * (vb128 - vb64)         # 2 x 7 basis vectors + 1 costate
     assert lib.kg_states_bytes(ctypes.byref(h), 100, 0, _lib.KG_C128) == 100 * vb128
-    # checkpoints every 20: 4 checkpoints below the last segment + 20 buffer slots
-    assert lib.kg_states_bytes(ctypes.byref(h), 100, 20, _lib.KG_C64) == 24 * vb64
-    assert lib.kg_states_bytes(ctypes.byref(h), 101, 20, _lib.KG_C64) == 25 * vb64
+    # checkpoints every 20: 4 checkpoints below the last segment + 2 x 20 buffer slots
+    assert lib.kg_states_bytes(ctypes.byref(h), 100, 20, _lib.KG_C64) == 44 * vb64
+    assert lib.kg_states_bytes(ctypes.byref(h), 101, 20, _lib.KG_C64) == 45 * vb64
+    assert lib.kg_states_bytes(ctypes.byref(h), 100, 100, _lib.KG_C64) == 100 * vb64
     assert lib.kg_states_bytes(ctypes.byref(h), 10, 11, _lib.KG_C64) == 0
     assert lib.kg_workspace_bytes(ctypes.byref(h), ctypes.byref(kry(m=0)), _lib.KG_C64) == 0
 

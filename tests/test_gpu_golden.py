@@ -1,0 +1,74 @@
+"""GPU results at the workloads' real sizes against the oracle's stored values
+(tests/golden/*.json, written by tests/golden/make_golden.py from the oracle
+alone): the L=16 gradient-ascent run, and short-N instances of the L=24 chain."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2010_03598_amd as kg
+import workloads
+from tests.gpu_util import C64, C128, dev_vec, host, rel_err, xxz_of
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as fh:
+        return json.load(fh)
+
+
+def psi_at(states, j, N, ckpt_every, D):
+    """Slot of psi_j in a state buffer (store-all layout)."""
+    assert ckpt_every == 0
+    return states[(j - 1) * D: j * D]
+
+
+@pytest.mark.parametrize("dtype,tol", [(C128, 1e-10), (C64, 1e-4)])
+def test_large_chain_short_N(dtype, tol):
+    """L=24 (D = 16,777,216), m=24, 2 slices: F, beta, gradient and sampled psi_N."""
+    gold = load_golden("large_short")
+    c = workloads.large(N=2)
+    h = xxz_of(c)
+    u = torch.tensor(c.u, dtype=torch.float64, device="cuda")
+    r = kg.grape_gradient(h, u, c.dt, kg.Krylov(c.m), dev_vec(c.psi0, dtype),
+                          dev_vec(c.target, dtype))
+    F = float(host(r.F))
+    assert abs(F - gold["F"]) / gold["F"] <= tol
+    assert rel_err(host(r.grad), np.array(gold["grad"])) <= tol
+    b = host(r.beta)
+    assert abs(complex(b[0], b[1]) - complex(*gold["beta"])) / abs(complex(*gold["beta"])) <= tol
+    rows = torch.tensor(gold["psi_N_rows"], device="cuda")
+    psi = psi_at(r.states, c.N, c.N, 0, c.D)[rows]
+    ref = np.array(gold["psi_N_re"]) + 1j * np.array(gold["psi_N_im"])
+    # amplitudes are ~D^-1/2; compare against the vector's scale
+    assert np.abs(host(psi) - ref).max() <= tol * 2.0 ** (-c.L / 2) * 10
+
+
+def test_ascent_run_every_iteration():
+    """L=16 chain, 20 steepest-ascent steps u <- u + eta g/max|g| on the device; F and
+    the gradient match the oracle's run at every iteration."""
+    gold = load_golden("ascent")
+    c = workloads.ascent()
+    h = xxz_of(c)
+    k = kg.Krylov(c.m)
+    u = torch.tensor(c.u, dtype=torch.float64, device="cuda")
+    psi0, f = dev_vec(c.psi0), dev_vec(c.target)
+    ws = kg.Workspace(h, k, C128)
+    states = kg.new_states(h, c.N, 0, C128)
+    Fs = []
+    for it in range(gold["steps"]):
+        r = kg.grape_gradient(h, u, c.dt, k, psi0, f, states=states, workspace=ws)
+        F = float(host(r.F))
+        g = host(r.grad)
+        assert abs(F - gold["F"][it]) / gold["F"][it] <= 1e-9, it
+        assert rel_err(g, np.array(gold["grad"][it])) <= 1e-9, it
+        Fs.append(F)
+        kg.grape_ascent_update(u, r.grad, gold["eta"])
+    assert np.abs(host(u) - np.array(gold["u_final"])).max() <= 1e-9
+    assert Fs[-1] > Fs[0]
