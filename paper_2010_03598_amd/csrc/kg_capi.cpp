@@ -152,7 +152,7 @@ kg_status carve(void* ws, size_t ws_bytes, const kg_xxz* h, const kg_krylov* k, 
     o->st = reinterpret_cast<KState*>(q);
     q += align_up(sizeof(KState), 256);
     o->partials = reinterpret_cast<cplx_d*>(q);
-    q += align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256);
+    q += align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
     o->basis = q;
     o->lam = p + 2 * slot_bytes(h, k, prec);
   }
@@ -358,7 +358,7 @@ void profiler_stop(Profiler* p, hipStream_t s, int cls, double bytes) {
 size_t vec_bytes(int L, int prec) { return ((size_t)1 << L) * (prec == KG_C128 ? 16 : 8); }
 
 size_t ws_fixed_bytes() {
-  return align_up(sizeof(KState), 256) + align_up(sizeof(cplx_d) * kMaxGrid * kMaxScal, 256);
+  return align_up(sizeof(KState), 256) + align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
 }
 
 Geo make_geo(int L, int prec, int tile_bits_override) {
@@ -367,7 +367,9 @@ Geo make_geo(int L, int prec, int tile_bits_override) {
   g.L = L;
   g.D = 1u << L;
   const int tb_max = 12;
-  int tb = L - 10;
+  // default tile (measured): complex128 takes the largest tile; complex64
+  // one size smaller, and 2^10 amplitudes once the chain has 2^23 or more
+  int tb = (prec == KG_C128) ? L - 8 : (L >= 23 ? 10 : L - 9);
   if (tile_bits_override >= 6) tb = tile_bits_override;
   if (tb > tb_max) tb = tb_max;
   if (tb > L) tb = L;
@@ -375,7 +377,7 @@ Geo make_geo(int L, int prec, int tile_bits_override) {
   // amplitudes per thread (2^RB) grow with the tile until register pressure
   // limits them; the rest of the tile is spread over up to 16 wavefronts
   static const int rb_c64[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
-  static const int rb_c128[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2};
+  static const int rb_c128[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
   g.TB = tb;
   g.RB = (prec == KG_C128) ? rb_c128[tb] : rb_c64[tb];
   g.WB = tb - 6 - g.RB;

@@ -61,51 +61,26 @@ __device__ __forceinline__ void complete_stores() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Deterministic grid-wide sum of `ns` complex FP64 values.  Every block
-// passes its block totals in `tot` (LDS); `b` is the block's index among the
-// G blocks that reduce together.  Returns true in exactly one block, the last
-// to arrive, with the grid totals in `tot`.  The last block adds the partials
-// in a fixed order (lane l takes blocks l, l+64, ...; then a fixed butterfly).
-//
-// The partials travel only through device-scope (sc1) stores and loads, which
-// are coherent across the XCDs' L2 caches; the stores are waited for before
-// the arrival counter is incremented.  No device-wide fence is needed, so the
-// L2 caches are never written back or invalidated here.
-__device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* counter, uint32_t b,
-                            uint32_t G) {
-  __shared__ int last;
-  if (G == 1) return true;
+// Sum of `ns` complex values over `cnt` rows of a partials table (row stride
+// kMaxScal) read with device-scope loads; the calling block's wavefronts share
+// the scalars, lane l adds rows l, l+64, ... in order, 8 rows per round trip,
+// then a fixed butterfly.  Results in tot[j].
+__device__ void sum_rows(const cplx_d* rows, uint32_t cnt, int ns, cplx_d* tot) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if (wv == 0) {
-    for (int j = lane; j < ns; j += 64) {
-      st_agent(&partials[(size_t)b * kMaxScal + j].re, tot[j].re);
-      st_agent(&partials[(size_t)b * kMaxScal + j].im, tot[j].im);
-    }
-    complete_stores();
-    uint32_t prev = 0;
-    if (lane == 0)
-      prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    prev = __shfl(prev, 0, 64);
-    if (lane == 0) last = (prev == G - 1);
-  }
-  __syncthreads();
-  if (!last) return false;
-  if (threadIdx.x == 0) st_agent_u32(counter, 0u);
   for (int j = wv; j < ns; j += nw) {
     double re = 0.0, im = 0.0;
-    // lane l adds blocks l, l+64, l+128, ... in order; 8 blocks per round trip
-    for (uint32_t b0 = 0; b0 < G; b0 += 8 * 64) {
+    for (uint32_t b0 = 0; b0 < cnt; b0 += 8 * 64) {
       double pr[8], pi[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const uint32_t blk = b0 + q * 64 + lane;
-        const cplx_d* p = &partials[(size_t)min(blk, G - 1) * kMaxScal + j];
+        const uint32_t r = b0 + q * 64 + lane;
+        const cplx_d* p = &rows[(size_t)min(r, cnt - 1) * kMaxScal + j];
         pr[q] = ld_agent(&p->re);
         pi[q] = ld_agent(&p->im);
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const bool in = (b0 + q * 64 + lane) < G;
+        const bool in = (b0 + q * 64 + lane) < cnt;
         re += in ? pr[q] : 0.0;
         im += in ? pi[q] : 0.0;
       }
@@ -114,6 +89,72 @@ __device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* cou
     im = wave_sum(im);
     if (lane == 0) tot[j] = cplx_d{re, im};
   }
+}
+
+// Count this block's arrival; true in the block that arrives last of `cnt`.
+__device__ bool arrive_last(uint32_t* counter, uint32_t cnt) {
+  __shared__ int last;
+  const int lane = threadIdx.x & 63;
+  if ((threadIdx.x >> 6) == 0) {
+    complete_stores();
+    uint32_t prev = 0;
+    if (lane == 0)
+      prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    prev = __shfl(prev, 0, 64);
+    if (lane == 0) last = (prev == cnt - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  if (threadIdx.x == 0) st_agent_u32(counter, 0u);
+  return true;
+}
+
+constexpr uint32_t kReduceFlat = 512;  // largest grid reduced in one level
+constexpr uint32_t kGroup = 64;        // blocks per group of the two-level reduction
+
+// Deterministic grid-wide sum of `ns` complex FP64 values.  Every block
+// passes its block totals in `tot` (LDS); `b` is the block's index among the
+// G blocks that reduce together.  Returns true in exactly one block, the last
+// to arrive, with the grid totals in `tot`.  Up to kReduceFlat blocks the last
+// block adds all partials; larger grids add groups of kGroup blocks first (the
+// last block of each group), then the groups.  The order is fixed, so results
+// do not depend on which block arrives last.
+//
+// The partials travel only through device-scope (sc1) stores and loads, which
+// are coherent across the XCDs' L2 caches; the stores are waited for before
+// the arrival counter is incremented.  No device-wide fence is needed, so the
+// L2 caches are never written back or invalidated here.  counters[0] counts
+// the top level, counters[1 + g] group g.
+__device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* counters, uint32_t b,
+                            uint32_t G) {
+  if (G == 1) return true;
+  const int lane = threadIdx.x & 63;
+  if ((threadIdx.x >> 6) == 0) {
+    for (int j = lane; j < ns; j += 64) {
+      st_agent(&partials[(size_t)b * kMaxScal + j].re, tot[j].re);
+      st_agent(&partials[(size_t)b * kMaxScal + j].im, tot[j].im);
+    }
+  }
+  if (G <= kReduceFlat) {
+    if (!arrive_last(&counters[0], G)) return false;
+    sum_rows(partials, G, ns, tot);
+    __syncthreads();
+    return true;
+  }
+  const uint32_t grp = b / kGroup, ngrp = (G + kGroup - 1) / kGroup;
+  const uint32_t gsize = min(kGroup, G - grp * kGroup);
+  if (!arrive_last(&counters[1 + grp], gsize)) return false;
+  sum_rows(partials + (size_t)grp * kGroup * kMaxScal, gsize, ns, tot);
+  __syncthreads();
+  // group totals go to rows [G, G + ngrp) of the table
+  if ((threadIdx.x >> 6) == 0) {
+    for (int j = lane; j < ns; j += 64) {
+      st_agent(&partials[(size_t)(G + grp) * kMaxScal + j].re, tot[j].re);
+      st_agent(&partials[(size_t)(G + grp) * kMaxScal + j].im, tot[j].im);
+    }
+  }
+  if (!arrive_last(&counters[0], ngrp)) return false;
+  sum_rows(partials + (size_t)G * kMaxScal, ngrp, ns, tot);
   __syncthreads();
   return true;
 }
@@ -188,7 +229,7 @@ __device__ __forceinline__ uint32_t tile_of(const Geo& g, uint32_t it, uint32_t 
 template <typename R, int RB>
 struct FarSlots {
   static constexpr int units = 16 / ((1 << RB) * (int)(sizeof(R) / 4));
-  static constexpr int n = units > 4 ? 4 : (units < 1 ? 1 : units);
+  static constexpr int n = units > 8 ? 8 : (units < 1 ? 1 : units);
 };
 
 // Basis vectors fetched per round trip in the projection/update loops: about

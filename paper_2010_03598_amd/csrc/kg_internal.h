@@ -11,6 +11,7 @@ namespace kg {
 constexpr int kMaxM = 64;          // largest Krylov dimension
 constexpr int kMaxScal = kMaxM + 2;  // reduction scalars per pass (window + norm + spare)
 constexpr int kMaxGrid = 2048;     // largest grid of the reducing kernels
+constexpr int kPartialRows = kMaxGrid + kMaxGrid / 64;  // block rows + group rows
 
 struct cplx_d {                    // complex FP64 with a fixed layout
   double re, im;
@@ -33,8 +34,7 @@ struct KState {
   cplx_d overlap;         // beta = <f|psi_N>
   double fid;
   double pad2_;
-  uint32_t counter;        // arrivals in the running grid reduction
-  uint32_t pad3_[3];
+  uint32_t counters[kMaxGrid / 64 + 4];  // arrivals in the running grid reduction
 };
 
 struct HvArgs {            // the Hamiltonian H0 + u Hc of one chain
@@ -66,7 +66,7 @@ int stream_grid(uint32_t D);
 
 struct Workspace {         // carved from the caller's workspace
   KState* st;
-  cplx_d* partials;        // [kMaxGrid][kMaxScal]
+  cplx_d* partials;        // [kPartialRows][kMaxScal]
   void* basis;             // m-1 vectors (stored Krylov vectors 1..m-1)
   void* lam;               // one vector (costate)
 };

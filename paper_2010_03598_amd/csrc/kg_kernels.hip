@@ -227,7 +227,7 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   if (lane == 0) wacc[wv * kMaxScal + nwin] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, ns, tot);
-  if (!grid_reduce(tot, ns, a.partials, &a.st->counter, bl, G)) return;
+  if (!grid_reduce(tot, ns, a.partials, a.st->counters, bl, G)) return;
   if (threadIdx.x >= 64) return;
 
   // ---- scalar update on wavefront 0 of the last block
@@ -373,7 +373,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, 1, tot);
-  if (!grid_reduce(tot, 1, a.partials, &a.st->counter, bl, G)) return;
+  if (!grid_reduce(tot, 1, a.partials, a.st->counters, bl, G)) return;
   if (threadIdx.x >= 64) return;
 
   KState* stw = a.st;
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(kStreamBlock)
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{sr, si};
   __syncthreads();
   block_totals(wacc, 1, tot);
-  if (!grid_reduce(tot, 1, partials, &st->counter, blockIdx.x, gridDim.x)) return;
+  if (!grid_reduce(tot, 1, partials, st->counters, blockIdx.x, gridDim.x)) return;
   if (threadIdx.x == 0) {
     const cplx_d b = tot[0];
     st->overlap = b;
@@ -575,7 +575,7 @@ __global__ void __launch_bounds__(kStreamBlock)
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{sr, si};
   __syncthreads();
   block_totals(wacc, 1, tot);
-  if (!grid_reduce(tot, 1, partials, &st->counter, blockIdx.x, gridDim.x)) return;
+  if (!grid_reduce(tot, 1, partials, st->counters, blockIdx.x, gridDim.x)) return;
   if (threadIdx.x == 0) {
     const double br = beta_dev[0], bi = beta_dev[1];
     const cplx_d B = tot[0];
@@ -609,8 +609,8 @@ __global__ void k_index_map(int L, uint32_t s0, uint32_t count, int32_t* n_anti,
 
 __global__ void k_init_state(KState* st) {
   const int i = threadIdx.x;
+  if (i < kMaxGrid / 64 + 4) st->counters[i] = 0u;
   if (i == 0) {
-    st->counter = 0u;
     st->done = 0;
     st->m_eff = 0;
     st->normT = 0.0;
