@@ -130,11 +130,12 @@ HvArgs make_hv(const kg_xxz* h, const double* u_ptr, double u_val) {
 }
 
 size_t slot_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
-  return ws_fixed_bytes() + align_up(vec_bytes(h->L, prec) * (size_t)(k->m - 1), 256);
+  return ws_fixed_bytes() + align_up(vec_bytes(h->L, prec) * (size_t)(k->m - 1), 256) +
+         align_up(vec_bytes(h->L, prec), 256);
 }
 
-// The workspace holds two Krylov slots (scalars, reduction partials and m-1
-// basis vectors each) and one costate vector.  Slot 0 serves single calls and
+// The workspace holds two Krylov slots (scalars, reduction partials, m-1
+// basis vectors and the H v_k vector each) and one costate vector.  Slot 0 serves single calls and
 // the backward sweep, slot 1 the segment recomputation advanced beside it.
 kg_status carve(void* ws, size_t ws_bytes, const kg_xxz* h, const kg_krylov* k, int32_t prec,
                 Workspace* out0, Workspace* out1) {
@@ -154,6 +155,8 @@ kg_status carve(void* ws, size_t ws_bytes, const kg_xxz* h, const kg_krylov* k, 
     o->partials = reinterpret_cast<cplx_d*>(q);
     q += align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
     o->basis = q;
+    q += align_up(vec_bytes(h->L, prec) * (size_t)(k->m - 1), 256);
+    o->hx = q;
     o->lam = p + 2 * slot_bytes(h, k, prec);
   }
   return KG_OK;

@@ -20,10 +20,12 @@
 //
 // Lanczos (App. A, Algorithm 2 with the full re-orthonormalisation it
 // describes).  One basis step is two passes over the tile grid:
-//   pass A(k): x = stored v_k; y = H x (recomputed from the tile);
+//   pass A(k): x = stored v_k; y = H x, stored (the H v vector);
 //              h_i = <v_i|y> for the projection window, and <x|x>;
 //   pass B(k): w = s_k y - sum_i (h_i s_i) v_i, stored unnormalised as v_{k+1},
-//              and ||w||^2.
+//              and ||w||^2; a streaming pass over y and the window.
+// Storing y costs one vector write and read; recomputing it in pass B would
+// repeat the partner-tile reads of the far hopping bonds, which cost more.
 // Stored vectors are not rescaled: scale_k = 1/||stored_k|| lives in device
 // memory and is folded into the coefficients.  Each pass ends with a
 // deterministic two-level grid reduction in FP64 (fixed order, no
@@ -87,6 +89,7 @@ struct LzArgs {
   Geo geo;
   const void* slot0;  // stored vector 0: the input of the Krylov call
   void* basis;        // stored vectors 1..m-1
+  void* hx;           // y = H v_k, written by pass A, read by pass B
   int32_t k;          // basis step
   int32_t i0;         // first index of the projection window [i0, k]
   int32_t m;
@@ -161,6 +164,20 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     if (it) __syncthreads();
     if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, a.k > 0 ? &a.st->done : nullptr)) return;
     const uint32_t base = tile << a.geo.TB;
+    if (a.k + 1 < a.m) {
+      // y for pass B (the last step has no pass B)
+      V* yv = reinterpret_cast<V*>(a.hx);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t s = base | eb | ((uint32_t)r << 6);
+        if (!a.geo.small || s < a.geo.D) {
+          V o;
+          o.x = T.yr[r];
+          o.y = T.yi[r];
+          yv[s] = o;
+        }
+      }
+    }
     // window vectors other than v_k, NW per round trip
     constexpr int NW = WinSlots<R, RB>::n;
     for (int i = a.i0; i < a.k; i += NW) {
@@ -289,8 +306,8 @@ template <typename R, int RB>
 __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
+  constexpr int NW = WinSlots<R, RB>::n;
   extern __shared__ unsigned char smem_raw[];
-  V* lds = reinterpret_cast<V*>(smem_raw);
   __shared__ cplx_d tot[kMaxScal];
 
   const uint32_t lane = threadIdx.x & 63u;
@@ -299,25 +316,35 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   double acc_nn = 0.0;
 
   const KState* st = a.st;
-  const double sk = st->scale[a.k];
-  const double u = control_value(a.hv);
   const V* x = slot_ptr<V>(a, a.k);
+  const V* yv = reinterpret_cast<const V*>(a.hx);
   V* out = reinterpret_cast<V*>(a.basis) + (size_t)a.k * a.geo.D;
   const uint32_t iters = a.geo.ntiles / G;
-  Tile<R, RB> T;
+  // same block-to-tile map as pass A, so y is read back from the L2 that wrote it
   for (uint32_t it = 0; it < iters; ++it) {
-    const uint32_t tile = tile_of(a.geo, it, bl, G);
-    if (it) __syncthreads();
-    if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, &a.st->done)) return;
-    const uint32_t base = tile << a.geo.TB;
-    double zr[NR], zi[NR];
+    const uint32_t base = tile_of(a.geo, it, bl, G) << a.geo.TB;
+    V yo[NR], xo[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      zr[r] = sk * (double)T.yr[r];
-      zi[r] = sk * (double)T.yi[r];
+      const uint32_t s = base | eb | ((uint32_t)r << 6);
+      const bool ok = !a.geo.small || s < a.geo.D;
+      yo[r] = ok ? yv[s] : V{(R)0, (R)0};
+      xo[r] = ok ? x[s] : V{(R)0, (R)0};
+    }
+    // a finished basis (breakdown in an earlier step) leaves nothing to do
+    if (it == 0 && st->done) return;
+    const double sk = st->scale[a.k];
+    double zr[NR], zi[NR];
+    {
+      const cplx_d c = st->coef[a.k - a.i0];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const double vr = xo[r].x, vi = xo[r].y;
+        zr[r] = sk * (double)yo[r].x - (c.re * vr - c.im * vi);
+        zi[r] = sk * (double)yo[r].y - (c.re * vi + c.im * vr);
+      }
     }
     // window vectors other than v_k, NW per round trip
-    constexpr int NW = WinSlots<R, RB>::n;
     for (int i = a.i0; i < a.k; i += NW) {
       V q[NW][NR];
 #pragma unroll
@@ -345,15 +372,6 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
         }
       }
     }
-    {
-      const cplx_d c = st->coef[a.k - a.i0];
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const double vr = T.xr[r], vi = T.xi[r];
-        zr[r] -= c.re * vr - c.im * vi;
-        zi[r] -= c.re * vi + c.im * vr;
-      }
-    }
     double nn = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -368,7 +386,6 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
     }
     acc_nn += wave_sum(nn);
   }
-  __syncthreads();
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{acc_nn, 0.0};
   __syncthreads();
@@ -651,7 +668,8 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
   if (pass_a) {
     hipLaunchKernelGGL((k_pass_a<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
   } else {
-    hipLaunchKernelGGL((k_pass_b<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
+    const size_t red = ((size_t)1 << g.WB) * kMaxScal * sizeof(cplx_d);
+    hipLaunchKernelGGL((k_pass_b<R, RB>), grid, block, red, s, lb);
   }
   return hipGetLastError();
 }
@@ -682,6 +700,7 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     la.geo = calls[j].geo;
     la.slot0 = calls[j].v_in;
     la.basis = wss[j]->basis;
+    la.hx = wss[j]->hx;
     la.m = calls[j].m;
     la.t = calls[j].t;
     la.tol = calls[j].tol;
@@ -702,13 +721,14 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     const int nwin = k - i0 + 1;
     if (prof) profiler_start(prof, s);
     if ((e = launch_pass_r<R>(true, lb, n, s)) != hipSuccess) return e;
-    // algorithmic bytes: the window vectors (v_k included) are read once
-    if (prof) profiler_stop(prof, s, kProfPassA, nwin * vb);
+    // algorithmic bytes: the window vectors (v_k included) are read once and
+    // y = H v_k is written (not in the last step)
+    if (prof) profiler_stop(prof, s, kProfPassA, (nwin + (last ? 0 : 1)) * vb);
     if (!last) {
       if (prof) profiler_start(prof, s);
       if ((e = launch_pass_r<R>(false, lb, n, s)) != hipSuccess) return e;
-      // the window vectors are read and v_{k+1} is written
-      if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 1) * vb);
+      // y and the window vectors are read, v_{k+1} is written
+      if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 2) * vb);
     }
   }
   const uint32_t D = c0.geo.D;
