@@ -61,33 +61,67 @@ __device__ __forceinline__ void complete_stores() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Sum of `ns` complex values over `cnt` rows of a partials table (row stride
-// kMaxScal) read with device-scope loads; the calling block's wavefronts share
-// the scalars, lane l adds rows l, l+64, ... in order, 8 rows per round trip,
-// then a fixed butterfly.  Results in tot[j].
-__device__ void sum_rows(const cplx_d* rows, uint32_t cnt, int ns, cplx_d* tot) {
+// Columns j of a partials table summed over `cnt` rows: j < ns from `rows`
+// (row stride kMaxScal), j == ns (when `xrows` is given) from column 0 of
+// `xrows` (same row stride).  Lane l adds rows l, l+64, ... in order, then a
+// fixed butterfly; the block's wavefronts share the columns.  Loads are
+// device-scope, and the loads of a batch of JB columns (RPL rows per lane
+// each) are all issued before any is used: one memory round trip per batch.
+template <int RPL, int JB>
+__device__ void sum_rows_t(const cplx_d* rows, uint32_t cnt, int ns, const cplx_d* xrows,
+                           cplx_d* tot) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  for (int j = wv; j < ns; j += nw) {
-    double re = 0.0, im = 0.0;
-    for (uint32_t b0 = 0; b0 < cnt; b0 += 8 * 64) {
-      double pr[8], pi[8];
+  const int nc = ns + (xrows ? 1 : 0);
+  for (int j0 = wv; j0 < nc; j0 += nw * JB) {
+    double re[JB], im[JB];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const uint32_t r = b0 + q * 64 + lane;
-        const cplx_d* p = &rows[(size_t)min(r, cnt - 1) * kMaxScal + j];
-        pr[q] = ld_agent(&p->re);
-        pi[q] = ld_agent(&p->im);
+    for (int c = 0; c < JB; ++c) re[c] = im[c] = 0.0;
+    for (uint32_t b0 = 0; b0 < cnt; b0 += RPL * 64) {
+      double pr[JB][RPL], pi[JB][RPL];
+#pragma unroll
+      for (int c = 0; c < JB; ++c) {
+        const int j = j0 + c * nw;
+        const cplx_d* base = (j < ns) ? rows + j : xrows;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const uint32_t r = min(b0 + q * 64 + lane, cnt - 1);
+          const cplx_d* p = base + (size_t)r * kMaxScal;
+          pr[c][q] = (j < nc) ? ld_agent(&p->re) : 0.0;
+          pi[c][q] = (j < nc) ? ld_agent(&p->im) : 0.0;
+        }
       }
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const bool in = (b0 + q * 64 + lane) < cnt;
-        re += in ? pr[q] : 0.0;
-        im += in ? pi[q] : 0.0;
+      for (int c = 0; c < JB; ++c) {
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const bool in = (b0 + q * 64 + lane) < cnt;
+          re[c] += in ? pr[c][q] : 0.0;
+          im[c] += in ? pi[c][q] : 0.0;
+        }
       }
     }
-    re = wave_sum(re);
-    im = wave_sum(im);
-    if (lane == 0) tot[j] = cplx_d{re, im};
+#pragma unroll
+    for (int c = 0; c < JB; ++c) {
+      const int j = j0 + c * nw;
+      const double sr = wave_sum(re[c]);
+      const double si = wave_sum(im[c]);
+      if (j < nc && lane == 0) tot[j] = cplx_d{sr, si};
+    }
+  }
+}
+
+// sum_rows_t with the batch shape chosen for the row count: about 16 loads
+// in flight per lane.
+__device__ void sum_rows(const cplx_d* rows, uint32_t cnt, int ns, const cplx_d* xrows,
+                         cplx_d* tot) {
+  if (cnt <= 64) {
+    sum_rows_t<1, 8>(rows, cnt, ns, xrows, tot);
+  } else if (cnt <= 128) {
+    sum_rows_t<2, 4>(rows, cnt, ns, xrows, tot);
+  } else if (cnt <= 256) {
+    sum_rows_t<4, 2>(rows, cnt, ns, xrows, tot);
+  } else {
+    sum_rows_t<8, 1>(rows, cnt, ns, xrows, tot);
   }
 }
 
@@ -118,7 +152,9 @@ constexpr uint32_t kGroup = 64;        // blocks per group of the two-level redu
 // to arrive, with the grid totals in `tot`.  Up to kReduceFlat blocks the last
 // block adds all partials; larger grids add groups of kGroup blocks first (the
 // last block of each group), then the groups.  The order is fixed, so results
-// do not depend on which block arrives last.
+// do not depend on which block arrives last.  When `xrows` is given (one
+// value per block in column 0, row stride kMaxScal, written by an earlier
+// kernel) its sum over the G blocks lands in tot[ns] by the same scheme.
 //
 // The partials travel only through device-scope (sc1) stores and loads, which
 // are coherent across the XCDs' L2 caches; the stores are waited for before
@@ -126,9 +162,13 @@ constexpr uint32_t kGroup = 64;        // blocks per group of the two-level redu
 // L2 caches are never written back or invalidated here.  counters[0] counts
 // the top level, counters[1 + g] group g.
 __device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* counters, uint32_t b,
-                            uint32_t G) {
-  if (G == 1) return true;
+                            uint32_t G, const cplx_d* xrows = nullptr) {
   const int lane = threadIdx.x & 63;
+  if (G == 1) {
+    if (xrows && threadIdx.x == 0) tot[ns] = cplx_d{ld_agent(&xrows[0].re), ld_agent(&xrows[0].im)};
+    __syncthreads();
+    return true;
+  }
   if ((threadIdx.x >> 6) == 0) {
     for (int j = lane; j < ns; j += 64) {
       st_agent(&partials[(size_t)b * kMaxScal + j].re, tot[j].re);
@@ -137,24 +177,26 @@ __device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* cou
   }
   if (G <= kReduceFlat) {
     if (!arrive_last(&counters[0], G)) return false;
-    sum_rows(partials, G, ns, tot);
+    sum_rows(partials, G, ns, xrows, tot);
     __syncthreads();
     return true;
   }
   const uint32_t grp = b / kGroup, ngrp = (G + kGroup - 1) / kGroup;
   const uint32_t gsize = min(kGroup, G - grp * kGroup);
   if (!arrive_last(&counters[1 + grp], gsize)) return false;
-  sum_rows(partials + (size_t)grp * kGroup * kMaxScal, gsize, ns, tot);
+  sum_rows(partials + (size_t)grp * kGroup * kMaxScal, gsize, ns,
+           xrows ? xrows + (size_t)grp * kGroup * kMaxScal : nullptr, tot);
   __syncthreads();
-  // group totals go to rows [G, G + ngrp) of the table
+  // group totals (and the extra column's) go to rows [G, G + ngrp) of the table
+  const int nc = ns + (xrows ? 1 : 0);
   if ((threadIdx.x >> 6) == 0) {
-    for (int j = lane; j < ns; j += 64) {
+    for (int j = lane; j < nc; j += 64) {
       st_agent(&partials[(size_t)(G + grp) * kMaxScal + j].re, tot[j].re);
       st_agent(&partials[(size_t)(G + grp) * kMaxScal + j].im, tot[j].im);
     }
   }
   if (!arrive_last(&counters[0], ngrp)) return false;
-  sum_rows(partials + (size_t)G * kMaxScal, ngrp, ns, tot);
+  sum_rows(partials + (size_t)G * kMaxScal, ngrp, nc, nullptr, tot);
   __syncthreads();
   return true;
 }

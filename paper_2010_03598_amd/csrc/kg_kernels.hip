@@ -23,7 +23,10 @@
 //   pass A(k): x = stored v_k; y = H x, stored (the H v vector);
 //              h_i = <v_i|y> for the projection window, and <x|x>;
 //   pass B(k): w = s_k y - sum_i (h_i s_i) v_i, stored unnormalised as v_{k+1},
-//              and ||w||^2; a streaming pass over y and the window.
+//              and the blocks' parts of ||w||^2; a streaming pass over y and
+//              the window.  The norm is summed by the finishing block of
+//              pass A(k+1), which needs it first, so pass B ends without a
+//              grid-wide reduction of its own.
 // Storing y costs one vector write and read; recomputing it in pass B would
 // repeat the partner-tile reads of the far hopping bonds, which cost more.
 // Stored vectors are not rescaled: scale_k = 1/||stored_k|| lives in device
@@ -102,6 +105,11 @@ struct LzArgs {
 
 constexpr int kMaxJobs = 2;
 
+// Column of the partials table that carries pass B's norm parts to the next
+// pass A (pass A's own partials use columns 0..m <= kMaxM).
+constexpr int kNormCol = kMaxScal - 1;
+static_assert(kNormCol > kMaxM, "norm column overlaps the window columns");
+
 // Independent Krylov calls of the same shape advanced by the same launches:
 // blocks [j*G, (j+1)*G) serve job j.
 struct LzBatch {
@@ -115,19 +123,22 @@ __device__ __forceinline__ const V* slot_ptr(const LzArgs& a, int i) {
 }
 
 // Scalar tail of a basis: exp(-itT) e_1 on wavefront 0 of the finishing block
-// and the combination coefficients dcomb_j = beta0 c_j scale_j.  `fresh_alpha`
-// replaces alpha[m_eff-1] when it was produced by this very kernel (NaN: read
-// it from memory); `fresh_s0`/`fresh_b0` likewise for step 0.
+// and the combination coefficients dcomb_j = beta0 c_j scale_j.  Values this
+// very kernel produced are passed in, since the wavefront's own stores are not
+// read back: `fresh_alpha` replaces alpha[m_eff-1], `fresh_b0`/`fresh_s0`
+// beta0 and scale_0 (NaN: read from memory), and for step kf >= 1 the pair
+// (`off_kf`, `scale_kf`) replaces offd[kf] and scale[kf] (kf < 0: none).
 __device__ void finish_basis(const LzArgs& a, int m_eff, double fresh_alpha, double fresh_b0,
-                             double fresh_s0) {
+                             double fresh_s0, int kf = -1, double off_kf = 0.0,
+                             double scale_kf = 0.0) {
   KState* st = a.st;
   const int i = threadIdx.x & 63;
   double ai = 0.0, lo = 0.0, hi = 0.0, sc = 0.0;
   if (i < m_eff) {
     ai = (i == m_eff - 1 && !isnan(fresh_alpha)) ? fresh_alpha : st->alpha[i];
-    lo = (i > 0) ? st->offd[i] : 0.0;
-    hi = (i + 1 < m_eff) ? st->offd[i + 1] : 0.0;
-    sc = (i == 0 && !isnan(fresh_s0)) ? fresh_s0 : st->scale[i];
+    lo = (i > 0) ? (i == kf ? off_kf : st->offd[i]) : 0.0;
+    hi = (i + 1 < m_eff) ? (i + 1 == kf ? off_kf : st->offd[i + 1]) : 0.0;
+    sc = (i == 0 && !isnan(fresh_s0)) ? fresh_s0 : (i == kf ? scale_kf : st->scale[i]);
   }
   const double b0 = isnan(fresh_b0) ? st->beta0 : fresh_b0;
   double cr, ci;
@@ -244,14 +255,17 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   if (lane == 0) wacc[wv * kMaxScal + nwin] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, ns, tot);
-  if (!grid_reduce(tot, ns, a.partials, a.st->counters, bl, G)) return;
+  // for k >= 1 the norm parts of pass B(k-1) are summed into tot[ns]
+  if (!grid_reduce(tot, ns, a.partials, a.st->counters, bl, G,
+                   a.k > 0 ? a.partials + kNormCol : nullptr))
+    return;
   if (threadIdx.x >= 64) return;
 
   // ---- scalar update on wavefront 0 of the last block
   KState* st = a.st;
   const int lane0 = threadIdx.x;
   const int k = a.k;
-  double sk, b0 = NAN, s0 = NAN;
+  double sk, b0 = NAN, s0 = NAN, bk = 0.0;
   if (k == 0) {
     const double nn = tot[nwin].re;
     if (!(nn > 0.0)) {
@@ -273,7 +287,18 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
       st->done = 0;
     }
   } else {
-    sk = st->scale[k];
+    // ||w|| of pass B(k-1): the off-diagonal entry of step k, or a breakdown
+    // (an invariant Krylov space of dimension k)
+    bk = sqrt(tot[ns].re);
+    if (bk <= a.tol * fmax(1.0, st->normT)) {
+      finish_basis(a, k, NAN, NAN, NAN);
+      return;
+    }
+    sk = 1.0 / bk;
+    if (lane0 == 0) {
+      st->offd[k] = bk;
+      st->scale[k] = sk;
+    }
   }
   for (int l = lane0; l < nwin; l += 64) {
     const int i = a.i0 + l;
@@ -282,14 +307,14 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     st->coef[l] = cplx_d{tot[l].re * f * si, tot[l].im * f * si};
   }
   const double alpha = tot[nwin - 1].re * sk * sk;
-  const double offk = (k == 0) ? 0.0 : st->offd[k];
+  const double offk = (k == 0) ? 0.0 : bk;
   const double prevT = (k == 0) ? 0.0 : st->normT;
   const double normT = fmax(prevT, fabs(alpha) + offk);
   if (lane0 == 0) {
     st->alpha[k] = alpha;
     st->normT = normT;
   }
-  if (k == a.m - 1) finish_basis(a, a.m, alpha, b0, s0);
+  if (k == a.m - 1) finish_basis(a, a.m, alpha, b0, s0, k, bk, sk);
 }
 
 template <typename R, int RB>
@@ -390,17 +415,10 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   if (lane == 0) wacc[wv * kMaxScal] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, 1, tot);
-  if (!grid_reduce(tot, 1, a.partials, a.st->counters, bl, G)) return;
-  if (threadIdx.x >= 64) return;
-
-  KState* stw = a.st;
-  const double b = sqrt(tot[0].re);
-  const double normT = stw->normT;
-  if (b <= a.tol * fmax(1.0, normT)) {
-    finish_basis(a, a.k + 1, NAN, NAN, NAN);
-  } else if (threadIdx.x == 0) {
-    stw->offd[a.k + 1] = b;
-    stw->scale[a.k + 1] = 1.0 / b;
+  // this block's part of ||w||^2, summed by the finishing block of pass A(k+1)
+  if (threadIdx.x == 0) {
+    st_agent(&a.partials[(size_t)bl * kMaxScal + kNormCol].re, tot[0].re);
+    st_agent(&a.partials[(size_t)bl * kMaxScal + kNormCol].im, 0.0);
   }
 }
 
