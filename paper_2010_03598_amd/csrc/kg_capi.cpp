@@ -370,9 +370,15 @@ Geo make_geo(int L, int prec, int tile_bits_override) {
   g.L = L;
   g.D = 1u << L;
   const int tb_max = 12;
-  // default tile (measured): complex128 takes the largest tile; complex64
-  // one size smaller, and 2^10 amplitudes once the chain has 2^23 or more
-  int tb = (prec == KG_C128) ? L - 8 : (L >= 23 ? 10 : L - 9);
+  // default tile, from Krylov-call timings at L = 16..24: complex64 takes
+  // 2^9..2^11 amplitudes (2^10 from L = 23 on), complex128 2^9..2^10 up to
+  // L = 19 and the largest tile from L = 20 on
+  int tb;
+  if (prec == KG_C128) {
+    tb = (L >= 20) ? 12 : std::min(std::max(L - 8, 9), 12);
+  } else {
+    tb = (L >= 23) ? 10 : std::min(std::max(L - 7, 9), 11);
+  }
   if (tile_bits_override >= 6) tb = tile_bits_override;
   if (tb > tb_max) tb = tb_max;
   if (tb > L) tb = L;

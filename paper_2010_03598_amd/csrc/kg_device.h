@@ -26,10 +26,29 @@ struct VT<double> {
 
 // ---------------------------------------------------------------------- helpers
 
+// v read from another lane by a DPP move (both 32-bit halves); lanes outside
+// ROW_MASK receive +0.0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane.  DPP steps in a fixed
+// order: pairs and quads (quad permutations), rows of 16 (row rotations by 4
+// and 8), then the row broadcasts of lanes 15 and 31 carry the partial sums
+// up to lane 63, whose value is broadcast.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f64<0xB1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_f64<0x4E>(v);        // quad_perm [2,3,0,1]
+  v += dpp_f64<0x124>(v);       // row_ror:4
+  v += dpp_f64<0x128>(v);       // row_ror:8
+  v += dpp_f64<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
