@@ -98,6 +98,41 @@ def time_hv(kg, torch, L, dtype, reps=50):
             "algorithmic_GBps": (r["bytes"] / r["launches"]) / per / 1e9}
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_a_L20_c64_traffic.md")
+KERNEL_OF_CLASS = {"pass_a": "k_pass_a", "pass_b": "k_pass_b", "combine": "k_combine"}
+
+
+def sources_sha256():
+    """Hash of the HIP/C++ sources the counters in TRAFFIC_FILE were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2010_03598_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(cls):
+    """HBM bytes per launch of a kernel class from the committed rocprofv3 counter
+    summary, or None when it was taken on other sources (or is missing)."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            text = fh.read()
+    except OSError:
+        return None
+    tag = "<!-- traffic-json: "
+    if tag not in text:
+        return None
+    rec = json.loads(text.split(tag, 1)[1].split(" -->", 1)[0])
+    if rec.get("sources_sha256") != sources_sha256():
+        return None
+    k = rec.get("per_kernel", {}).get(KERNEL_OF_CLASS.get(cls, ""))
+    return None if k is None else float(k["hbm_bytes_per_launch"])
+
+
 def cpu_baseline(c, budget_s=20.0):
     """The oracle (NumPy/SciPy FP64) on a bounded prefix of the same workload:
     forward Krylov propagations of the first slices, extrapolated to the
@@ -242,7 +277,9 @@ def main():
         "hv": {"L20_c64": hv20, "L24_c64": hv24, "L24_c128": hv24_128,
                "peak_GBps": HBM_PEAK_GBS},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(dom),
+                     "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT),
                      "avg_us": per_launch_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "sampled_launches": d["launches"]},
         "kernels": classes,
