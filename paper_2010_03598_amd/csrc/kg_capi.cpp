@@ -370,14 +370,14 @@ Geo make_geo(int L, int prec, int tile_bits_override) {
   g.L = L;
   g.D = 1u << L;
   const int tb_max = 12;
-  // default tile, from Krylov-call timings at L = 16..24: complex64 takes
-  // 2^9..2^11 amplitudes (2^10 from L = 23 on), complex128 2^9..2^10 up to
-  // L = 19 and the largest tile from L = 20 on
+  // default tile, from Krylov-call timings at L = 16..24: 2^9..2^11
+  // amplitudes up to L = 18 (complex64) or L = 19 (complex128), the largest
+  // tile beyond
   int tb;
   if (prec == KG_C128) {
     tb = (L >= 20) ? 12 : std::min(std::max(L - 8, 9), 12);
   } else {
-    tb = (L >= 23) ? 10 : std::min(std::max(L - 7, 9), 11);
+    tb = (L >= 19) ? 12 : std::min(std::max(L - 7, 9), 11);
   }
   if (tile_bits_override >= 6) tb = tile_bits_override;
   if (tb > tb_max) tb = tb_max;
@@ -385,7 +385,7 @@ Geo make_geo(int L, int prec, int tile_bits_override) {
   if (tb < 6) tb = 6;
   // amplitudes per thread (2^RB) grow with the tile until register pressure
   // limits them; the rest of the tile is spread over up to 16 wavefronts
-  static const int rb_c64[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+  static const int rb_c64[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2};
   static const int rb_c128[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
   g.TB = tb;
   g.RB = (prec == KG_C128) ? rb_c128[tb] : rb_c64[tb];
