@@ -115,6 +115,73 @@ def test_zeroth_order_error_is_second_order_in_dt():
     assert all(3.5 < q < 4.5 for q in ratios), (errs, ratios)
 
 
+def test_centred_error_is_third_order_in_dt():
+    """The centred variant (App. B) falls ~8x per halving of dt on the same fixed-
+    horizon problem on which Eq. 5 falls ~4x, and it is the more accurate of the two."""
+    L, T = 6, 0.8
+    rng = np.random.default_rng(4)
+    H0, Hc = dense_parts(L, 1.0, 0.5, HC_SX, 1)
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    ch = chain_of(L, 1.0, 0.5, HC_SX, 1)
+    errs, errs0 = [], []
+    for dt in [0.1, 0.05, 0.025]:
+        N = int(round(T / dt))
+        t_mid = (np.arange(N) + 0.5) * dt
+        u = np.sin(2.0 * t_mid) + 0.5 * np.cos(5.0 * t_mid)
+        _, ge = exact.exact_gradient_dense(H0, Hc, u, psi0, f, dt)
+        rc = grape.gradient_centred(ch, u, psi0, f, dt, m=24)
+        r0 = grape.gradient(ch, u, psi0, f, dt, m=24)
+        errs.append(np.abs(rc.grad - ge).max())
+        errs0.append(np.abs(r0.grad - ge).max())
+        assert abs(rc.F - r0.F) < 1e-14
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    assert all(7.0 < q < 9.0 for q in ratios), (errs, ratios)
+    assert all(e < e0 / 5 for e, e0 in zip(errs, errs0)), (errs, errs0)
+
+
+@pytest.mark.parametrize("case", ["no_drift", "conserved_sz"])
+def test_centred_is_exact_when_control_commutes(case):
+    """With [Hc, H_j] = 0 the bracket is the same at both ends of a slice, so the
+    centred gradient, like Eq. 5, equals the exact one."""
+    L, N, dt = 5, 6, 0.4
+    rng = np.random.default_rng(22)
+    if case == "no_drift":
+        J, kind, sites = 0.0, HC_SX, 1 << 1
+    else:
+        J, kind, sites = 1.0, HC_SZ, (1 << L) - 1
+    H0, Hc = dense_parts(L, J, 0.5, kind, sites)
+    u = rng.uniform(-1, 1, N)
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    _, g_exact = exact.exact_gradient_dense(H0, Hc, u, psi0, f, dt)
+    r = grape.gradient_centred(chain_of(L, J, 0.5, kind, sites), u, psi0, f, dt, m=24)
+    assert np.abs(r.grad - g_exact).max() < 1e-12 * max(1.0, np.abs(g_exact).max())
+    assert np.abs(g_exact).max() > 1e-3
+
+
+def test_centred_single_slice_is_trapezoid_of_exact_integrand():
+    """N = 1: the exact derivative is -i int_0^dt <e^{iH(dt-s)} f|Hc|e^{-iHs} psi0> ds
+    (App. B, natural gradient); the centred value is the trapezoid rule of that
+    integrand (end points s = 0 and s = dt), computed here from dense propagators."""
+    L, dt = 5, 0.3
+    rng = np.random.default_rng(23)
+    H0, Hc = dense_parts(L, 1.0, 0.7, HC_SX, 1)
+    u = np.array([0.4])
+    psi0 = workloads.random_state(rng, 1 << L)
+    f = workloads.random_state(rng, 1 << L)
+    H = H0 + u[0] * Hc
+    U = exact.propagator(H, dt)
+    beta = np.vdot(f, U @ psi0)
+    def integrand(s):
+        a = exact.propagator(H, -(dt - s)) @ f      # e^{+iH(dt-s)} f
+        b = exact.propagator(H, s) @ psi0          # e^{-iHs} psi0
+        return 2.0 * (np.conj(beta) * (-1j) * np.vdot(a, Hc @ b)).real
+    trap = 0.5 * dt * (integrand(0.0) + integrand(dt))
+    r = grape.gradient_centred(chain_of(L, 1.0, 0.7, HC_SX, 1), u, psi0, f, dt, m=24)
+    assert abs(r.grad[0] - trap) < 1e-12
+
+
 def test_gradient_ascent_direction_raises_fidelity():
     c = workloads.small()
     ch = chain_of(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
