@@ -10,6 +10,8 @@
  *                                                           (Algorithm 1, Eqs. 2, 4, B1, B2)
  *   grape_gradient  dF/du_j = 2 dt Im(conj(beta) <lambda_j|Hc|psi_j>)
  *                   with lambda_N = f, lambda_{j-1} = U_j^dagger lambda_j   (Eq. 5, Algorithm 1)
+ *   grape_gradient_centred  the same bracket at both ends of each slice, averaged
+ *                   (the centred variant of App. B, error O(dt^3) per slice)
  *   grape_ascent_update  u <- u + eta g / max|g|            (steepest ascent, Algorithm 1 update)
  *
  * Model.  Open chain of L spins 1/2, S = sigma/2:
@@ -158,6 +160,21 @@ kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double
                          double* F_dev, double* beta_dev, double* grad_dev, void* states,
                          int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
                          void* stream);
+
+/* Centred zeroth-order gradient (App. B, the centred variant of Eq. 5): the
+ * natural gradient of slice j evaluated at the slice centre, approximated by
+ * the mean of the Eq. 5 bracket at the two ends of the slice,
+ *   dF/du_j ~ (G_{j-1} + G_j) / 2,  G_j = 2 dt Im(conj(beta) <lambda_j|Hc|psi_j>),
+ * with G_0 from psi_0 and lambda_0 = U_1^dagger lambda_1 (one backward
+ * propagation more than grape_gradient).  Its error against the exact
+ * piecewise-constant gradient is O(dt^3) per slice instead of O(dt^2).
+ * Arguments, buffers and errors as grape_gradient; states left by
+ * grape_forward may be reused (states_valid = 1). */
+kg_status grape_gradient_centred(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                 const kg_krylov* k, int32_t prec, const void* psi0,
+                                 const void* target, double* F_dev, double* beta_dev,
+                                 double* grad_dev, void* states, int32_t ckpt_every,
+                                 int32_t states_valid, void* ws, size_t ws_bytes, void* stream);
 
 /* Steepest-ascent update u_j <- u_j + eta * g_j / max_i |g_i| on the device
  * (u unchanged when g = 0).  N >= 1.  Errors: KG_EINVAL, KG_EDEVICE. */

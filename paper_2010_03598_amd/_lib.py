@@ -71,6 +71,8 @@ SIGNATURES = {
     "grape_forward": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _I32, _P, _SZ, _P]),
     "grape_gradient": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _P, _I32, _I32,
                               _P, _SZ, _P]),
+    "grape_gradient_centred": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _P, _I32,
+                                      _I32, _P, _SZ, _P]),
     "grape_ascent_update": (_I32, [_P, _P, _I32, _D, _P]),
     "kg_debug_index_map": (_I32, [_I32, _U32, _U32, _P, _P, _P]),
     "kg_profile_begin": (_I32, [_I32, _I32]),

@@ -182,9 +182,11 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
                    target: torch.Tensor, ckpt_every: int = 0, states: Optional[torch.Tensor] = None,
                    states_valid: bool = False, beta: Optional[torch.Tensor] = None,
                    grad: Optional[torch.Tensor] = None, F: Optional[torch.Tensor] = None,
-                   workspace: Optional[Workspace] = None) -> GrapeResult:
-    """Fidelity and zeroth-order gradient dF/du_j (Eq. 5).  With states_valid, `states`
-    and `beta` must come from grape_forward with the same arguments."""
+                   workspace: Optional[Workspace] = None, centred: bool = False) -> GrapeResult:
+    """Fidelity and zeroth-order gradient dF/du_j (Eq. 5), or with `centred` its
+    centred variant (the bracket at both ends of each slice, averaged; App. B).
+    With states_valid, `states` and `beta` must come from grape_forward with the
+    same arguments."""
     dtype = psi0.dtype
     _vec(psi0, h, dtype, "psi0")
     _vec(target, h, dtype, "target")
@@ -207,7 +209,8 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
     if grad is None:
         grad = torch.empty(N, dtype=torch.float64, device=dev)
     _f64(grad, N, "grad")
-    _lib.check("grape_gradient", _lib.load().grape_gradient(
+    name = "grape_gradient_centred" if centred else "grape_gradient"
+    _lib.check(name, getattr(_lib.load(), name)(
         ctypes.byref(h.c()), _ptr(u), N, float(dt), ctypes.byref(k.c()), prec_of(dtype), _ptr(psi0),
         _ptr(target), _ptr(F), _ptr(beta), _ptr(grad), _ptr(states), int(ckpt_every),
         1 if states_valid else 0, ws.ptr, ws.nbytes, _stream()))

@@ -6,7 +6,8 @@ forward:  grape_forward (forward sweep of Algorithm 1 and the overlap of Eq. 2),
 backward: the library's adjoint sweep (grape_gradient with the saved states):
           costates lambda_j propagated backwards from the target, the earlier
           segments recomputed from their checkpoints beside it, and the
-          zeroth-order gradient of Eq. 5 per slice.
+          zeroth-order gradient of Eq. 5 per slice (with `centred`, its centred
+          variant from App. B, whose error is one order higher in dt).
 
 The backward returns the paper's zeroth-order gradient, not the exact
 derivative of the piecewise-constant propagation: the two differ by O(dt)
@@ -30,11 +31,11 @@ class GrapeFidelity(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u: torch.Tensor, h: XXZ, dt: float, k: Krylov, psi0: torch.Tensor,
                 target: torch.Tensor, ckpt_every: int = 0,
-                workspace: Optional[Workspace] = None):
+                workspace: Optional[Workspace] = None, centred: bool = False):
         u = u.detach().contiguous()
         ws = workspace if workspace is not None else Workspace(h, k, psi0.dtype, psi0.device)
         r = grape_forward(h, u, dt, k, psi0, target, ckpt_every=ckpt_every, workspace=ws)
-        ctx.h, ctx.dt, ctx.k, ctx.ckpt_every = h, dt, k, ckpt_every
+        ctx.h, ctx.dt, ctx.k, ctx.ckpt_every, ctx.centred = h, dt, k, ckpt_every, centred
         ctx.psi0, ctx.target, ctx.ws = psi0, target, ws
         ctx.states, ctx.beta = r.states, r.beta
         ctx.save_for_backward(u)
@@ -45,14 +46,15 @@ class GrapeFidelity(torch.autograd.Function):
         (u,) = ctx.saved_tensors
         r = grape_gradient(ctx.h, u, ctx.dt, ctx.k, ctx.psi0, ctx.target,
                            ckpt_every=ctx.ckpt_every, states=ctx.states, states_valid=True,
-                           beta=ctx.beta, workspace=ctx.ws)
+                           beta=ctx.beta, workspace=ctx.ws, centred=ctx.centred)
         grad_u = r.grad * gF.to(r.grad.dtype)
         ctx.states = None
-        return grad_u, None, None, None, None, None, None, None
+        return grad_u, None, None, None, None, None, None, None, None
 
 
 def fidelity(u: torch.Tensor, h: XXZ, dt: float, k: Krylov, psi0: torch.Tensor,
              target: torch.Tensor, ckpt_every: int = 0,
-             workspace: Optional[Workspace] = None) -> torch.Tensor:
-    """Differentiable fidelity; u is a float64 device tensor of N controls."""
-    return GrapeFidelity.apply(u, h, dt, k, psi0, target, ckpt_every, workspace)
+             workspace: Optional[Workspace] = None, centred: bool = False) -> torch.Tensor:
+    """Differentiable fidelity; u is a float64 device tensor of N controls.  The
+    backward gives the zeroth-order gradient, or its centred variant."""
+    return GrapeFidelity.apply(u, h, dt, k, psi0, target, ckpt_every, workspace, centred)

@@ -246,8 +246,11 @@ kg_status forward_sweep(const SweepArgs& a, const States& S, double* F_dev, doub
   return KG_OK;
 }
 
+// Costate sweep and brackets.  With `centred`, the sweep continues to
+// lambda_0 = U_1^dagger lambda_1, takes the bracket with psi_0 into KState::g0
+// and replaces every g_j by the mean of the brackets at the two ends of slice j.
 kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta_dev,
-                         double* grad_dev) {
+                         double* grad_dev, bool centred = false) {
   const HvArgs hc = make_hv(a.h, nullptr, 0.0);
   const void* lam = a.target;
   for (int q = S.nseg - 1; q >= 0; --q) {
@@ -266,7 +269,7 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
                             grad_dev + (j - 1), a.stream),
              "gradient bracket");
       if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * vec_bytes(a.h->L, a.prec));
-      if (j > 1) {
+      if (j > 1 || centred) {
         const KrylovCall cb = krylov_call(a, j, -a.dt, lam, a.ws.lam);
         if (recompute && re_i <= S.c - 1) {
           const int jr = rq * S.c + re_i;
@@ -286,6 +289,12 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
       KG_HIP(launch_krylov(cr, a.ws1, a.stream), "segment recomputation");
       re_in = S.at(jr);
     }
+  }
+  if (centred) {
+    KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, a.psi0, a.dt, beta_dev, a.ws, &a.ws.st->g0,
+                          a.stream),
+           "gradient bracket at t = 0");
+    KG_HIP(launch_centre(grad_dev, a.N, &a.ws.st->g0, a.stream), "centred gradient");
   }
   return KG_OK;
 }
@@ -493,11 +502,13 @@ kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double 
   return ok();
 }
 
-kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
-                         const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
-                         double* F_dev, double* beta_dev, double* grad_dev, void* states,
-                         int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
-                         void* stream) {
+namespace {
+
+kg_status gradient_impl(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                        const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                        double* F_dev, double* beta_dev, double* grad_dev, void* states,
+                        int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
+                        void* stream, bool centred, const char* name) {
   KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
   if (!beta_dev || !grad_dev) return fail(KG_EINVAL, "beta_dev and grad_dev are required");
   if (states_valid != 0 && states_valid != 1) return fail(KG_EINVAL, "states_valid must be 0 or 1");
@@ -506,11 +517,32 @@ kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double
   SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
               make_geo(h->L, prec, tile_override_from_env()), W, W1, (hipStream_t)stream};
   const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
-  KG_HIP(launch_init(W.st, a.stream), "grape_gradient init");
-  KG_HIP(launch_init(W1.st, a.stream), "grape_gradient init");
+  KG_HIP(launch_init(W.st, a.stream), name);
+  KG_HIP(launch_init(W1.st, a.stream), name);
   if (!states_valid) KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
-  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev));
+  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev, centred));
   return ok();
+}
+
+}  // namespace
+
+kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                         const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                         double* F_dev, double* beta_dev, double* grad_dev, void* states,
+                         int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
+                         void* stream) {
+  return gradient_impl(h, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev, states,
+                       ckpt_every, states_valid, ws, ws_bytes, stream, false, "grape_gradient");
+}
+
+kg_status grape_gradient_centred(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                 const kg_krylov* k, int32_t prec, const void* psi0,
+                                 const void* target, double* F_dev, double* beta_dev,
+                                 double* grad_dev, void* states, int32_t ckpt_every,
+                                 int32_t states_valid, void* ws, size_t ws_bytes, void* stream) {
+  return gradient_impl(h, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev, states,
+                       ckpt_every, states_valid, ws, ws_bytes, stream, true,
+                       "grape_gradient_centred");
 }
 
 kg_status grape_ascent_update(double* u_dev, const double* grad_dev, int32_t N, double eta,

@@ -33,7 +33,7 @@ struct KState {
   // GRAPE scalars
   cplx_d overlap;         // beta = <f|psi_N>
   double fid;
-  double pad2_;
+  double g0;              // centred gradient: the bracket at the start of slice 1
   uint32_t counters[kMaxGrid / 64 + 4];  // arrivals in the running grid reduction
 };
 
@@ -111,6 +111,7 @@ hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam
                           hipStream_t s);
 hipError_t launch_init(KState* st, hipStream_t s);
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
+hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s);
 
 // batched persistent form (kg_batched.hip); kg_chain comes from kgrape.h
 }  // namespace kg

@@ -633,6 +633,26 @@ __global__ void __launch_bounds__(1024) k_ascent(double* u, const double* g, int
   for (int j = threadIdx.x; j < N; j += blockDim.x) u[j] += f * g[j];
 }
 
+// Centred gradient from the end-point brackets, in place: on entry g[j-1] holds
+// the bracket at the end of slice j (j = 1..N) and *g0 the one at the start of
+// slice 1; on exit g[j-1] = (bracket at the start + bracket at the end) / 2.
+// One block walks the array from the top, 1024 entries at a time: every
+// thread reads its two inputs before any thread of the chunk writes, and the
+// chunk below has not been written yet.
+__global__ void __launch_bounds__(1024) k_centre(double* g, int N, const double* g0) {
+  for (int top = N; top > 0; top -= (int)blockDim.x) {
+    const int j = top - 1 - (int)threadIdx.x;   // 0-based slice index
+    double mid = 0.0;
+    if (j >= 0) {
+      const double lo = (j == 0) ? *g0 : g[j - 1];
+      mid = 0.5 * (lo + g[j]);
+    }
+    __syncthreads();
+    if (j >= 0) g[j] = mid;
+    __syncthreads();
+  }
+}
+
 __global__ void k_index_map(int L, uint32_t s0, uint32_t count, int32_t* n_anti, uint32_t* pmask) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -834,6 +854,11 @@ hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam
 
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s) {
   hipLaunchKernelGGL(k_ascent, dim3(1), dim3(1024), 0, s, u, g, N, eta);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s) {
+  hipLaunchKernelGGL(k_centre, dim3(1), dim3(1024), 0, s, g, N, g0);
   return hipGetLastError();
 }
 
