@@ -12,6 +12,8 @@
  *                   with lambda_N = f, lambda_{j-1} = U_j^dagger lambda_j   (Eq. 5, Algorithm 1)
  *   grape_gradient_centred  the same bracket at both ends of each slice, averaged
  *                   (the centred variant of App. B, error O(dt^3) per slice)
+ *   grape_gradient_quadrature  exact piecewise-constant gradient by Gauss-Legendre
+ *                   quadrature of the natural gradient inside each slice (App. B)
  *   grape_ascent_update  u <- u + eta g / max|g|            (steepest ascent, Algorithm 1 update)
  *
  * Model.  Open chain of L spins 1/2, S = sigma/2:
@@ -175,6 +177,26 @@ kg_status grape_gradient_centred(const kg_xxz* h, const double* u_dev, int32_t N
                                  const void* target, double* F_dev, double* beta_dev,
                                  double* grad_dev, void* states, int32_t ckpt_every,
                                  int32_t states_valid, void* ws, size_t ws_bytes, void* stream);
+
+/* Exact piecewise-constant gradient by Gauss-Legendre quadrature of the
+ * natural gradient inside each slice (App. B): with nodes s_q in (0, dt) and
+ * weights w_q of the n-point rule on [0, dt],
+ *   dF/du_j = sum_q 2 w_q Im(conj(beta) <e^{+i H_j (dt - s_q)} lambda_j | Hc |
+ *                                      e^{-i H_j s_q} psi_{j-1}>),
+ * the node states from Krylov propagations over partial steps (2n per slice).
+ * Its error is that of the n-point rule, O(dt^(2n+1)) per slice, plus the
+ * Krylov error, so it is the derivative of the forward's F to that accuracy.
+ * nodes: 1..KG_MAX_NODES.  The workspace must hold
+ * kg_quadrature_workspace_bytes (two node vectors beyond kg_workspace_bytes).
+ * Other arguments, buffers and errors as grape_gradient. */
+#define KG_MAX_NODES 16
+size_t kg_quadrature_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec);
+kg_status grape_gradient_quadrature(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                    const kg_krylov* k, int32_t prec, const void* psi0,
+                                    const void* target, double* F_dev, double* beta_dev,
+                                    double* grad_dev, void* states, int32_t ckpt_every,
+                                    int32_t states_valid, int32_t nodes, void* ws,
+                                    size_t ws_bytes, void* stream);
 
 /* Steepest-ascent update u_j <- u_j + eta * g_j / max_i |g_i| on the device
  * (u unchanged when g = 0).  N >= 1.  Errors: KG_EINVAL, KG_EDEVICE. */

@@ -84,12 +84,18 @@ def _f64(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
     return t
 
 
-class Workspace:
-    """Device scratch for krylov_expv / grape_forward / grape_gradient."""
+def _ws_bytes(h: XXZ, k: Krylov, dtype: torch.dtype, quadrature: bool) -> int:
+    fn = "kg_quadrature_workspace_bytes" if quadrature else "kg_workspace_bytes"
+    return int(getattr(_lib.load(), fn)(ctypes.byref(h.c()), ctypes.byref(k.c()), prec_of(dtype)))
 
-    def __init__(self, h: XXZ, k: Krylov, dtype: torch.dtype, device=None):
-        self.nbytes = int(_lib.load().kg_workspace_bytes(ctypes.byref(h.c()), ctypes.byref(k.c()),
-                                                         prec_of(dtype)))
+
+class Workspace:
+    """Device scratch for krylov_expv / grape_forward / grape_gradient (with
+    `quadrature`, large enough for the quadrature gradient as well)."""
+
+    def __init__(self, h: XXZ, k: Krylov, dtype: torch.dtype, device=None,
+                 quadrature: bool = False):
+        self.nbytes = _ws_bytes(h, k, dtype, quadrature)
         if self.nbytes == 0:
             raise ValueError(_lib.last_error() or "invalid chain or Krylov options")
         self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8,
@@ -97,9 +103,8 @@ class Workspace:
         off = (-self.buf.data_ptr()) % 256
         self.ptr = ctypes.c_void_p(self.buf.data_ptr() + off)
 
-    def fits(self, h: XXZ, k: Krylov, dtype: torch.dtype) -> bool:
-        need = _lib.load().kg_workspace_bytes(ctypes.byref(h.c()), ctypes.byref(k.c()),
-                                              prec_of(dtype))
+    def fits(self, h: XXZ, k: Krylov, dtype: torch.dtype, quadrature: bool = False) -> bool:
+        need = _ws_bytes(h, k, dtype, quadrature)
         return need != 0 and need <= self.nbytes
 
 
@@ -117,9 +122,10 @@ def new_states(h: XXZ, N: int, ckpt_every: int, dtype: torch.dtype, device=None)
     return torch.empty(nb // esz, dtype=dtype, device=device or torch.device("cuda"))
 
 
-def _ws(ws: Optional[Workspace], h: XXZ, k: Krylov, dtype, device) -> Workspace:
-    if ws is None or not ws.fits(h, k, dtype):
-        ws = Workspace(h, k, dtype, device)
+def _ws(ws: Optional[Workspace], h: XXZ, k: Krylov, dtype, device,
+        quadrature: bool = False) -> Workspace:
+    if ws is None or not ws.fits(h, k, dtype, quadrature):
+        ws = Workspace(h, k, dtype, device, quadrature)
     return ws
 
 
@@ -182,11 +188,16 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
                    target: torch.Tensor, ckpt_every: int = 0, states: Optional[torch.Tensor] = None,
                    states_valid: bool = False, beta: Optional[torch.Tensor] = None,
                    grad: Optional[torch.Tensor] = None, F: Optional[torch.Tensor] = None,
-                   workspace: Optional[Workspace] = None, centred: bool = False) -> GrapeResult:
-    """Fidelity and zeroth-order gradient dF/du_j (Eq. 5), or with `centred` its
-    centred variant (the bracket at both ends of each slice, averaged; App. B).
-    With states_valid, `states` and `beta` must come from grape_forward with the
-    same arguments."""
+                   workspace: Optional[Workspace] = None, centred: bool = False,
+                   nodes: int = 0) -> GrapeResult:
+    """Fidelity and gradient dF/du_j: the zeroth-order gradient of Eq. 5; with
+    `centred` its centred variant (the bracket at both ends of each slice,
+    averaged; App. B); with `nodes` > 0 the exact piecewise-constant gradient by
+    `nodes`-point Gauss-Legendre quadrature inside each slice.  With
+    states_valid, `states` and `beta` must come from grape_forward with the same
+    arguments."""
+    if centred and nodes:
+        raise ValueError("centred and nodes are exclusive")
     dtype = psi0.dtype
     _vec(psi0, h, dtype, "psi0")
     _vec(target, h, dtype, "target")
@@ -201,7 +212,7 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
         raise ValueError("states buffer too small")
     if states_valid and beta is None:
         raise ValueError("states_valid needs beta from grape_forward")
-    ws = _ws(workspace, h, k, dtype, dev)
+    ws = _ws(workspace, h, k, dtype, dev, quadrature=nodes > 0)
     if F is None:
         F = torch.empty((), dtype=torch.float64, device=dev)
     if beta is None:
@@ -209,11 +220,15 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
     if grad is None:
         grad = torch.empty(N, dtype=torch.float64, device=dev)
     _f64(grad, N, "grad")
-    name = "grape_gradient_centred" if centred else "grape_gradient"
-    _lib.check(name, getattr(_lib.load(), name)(
-        ctypes.byref(h.c()), _ptr(u), N, float(dt), ctypes.byref(k.c()), prec_of(dtype), _ptr(psi0),
-        _ptr(target), _ptr(F), _ptr(beta), _ptr(grad), _ptr(states), int(ckpt_every),
-        1 if states_valid else 0, ws.ptr, ws.nbytes, _stream()))
+    args = [ctypes.byref(h.c()), _ptr(u), N, float(dt), ctypes.byref(k.c()), prec_of(dtype),
+            _ptr(psi0), _ptr(target), _ptr(F), _ptr(beta), _ptr(grad), _ptr(states),
+            int(ckpt_every), 1 if states_valid else 0]
+    if nodes:
+        name = "grape_gradient_quadrature"
+        args.append(int(nodes))
+    else:
+        name = "grape_gradient_centred" if centred else "grape_gradient"
+    _lib.check(name, getattr(_lib.load(), name)(*args, ws.ptr, ws.nbytes, _stream()))
     return GrapeResult(F=F, beta=beta, grad=grad, states=states)
 
 

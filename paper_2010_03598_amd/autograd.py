@@ -7,13 +7,17 @@ backward: the library's adjoint sweep (grape_gradient with the saved states):
           costates lambda_j propagated backwards from the target, the earlier
           segments recomputed from their checkpoints beside it, and the
           zeroth-order gradient of Eq. 5 per slice (with `centred`, its centred
-          variant from App. B, whose error is one order higher in dt).
+          variant from App. B, whose error is one order higher in dt; with
+          `nodes` > 0, the exact piecewise-constant gradient by Gauss-Legendre
+          quadrature inside each slice, which torch.autograd.gradcheck accepts).
 
-The backward returns the paper's zeroth-order gradient, not the exact
-derivative of the piecewise-constant propagation: the two differ by O(dt)
-relative, so torch.autograd.gradcheck does not apply; the gradient is checked
+By default the backward returns the paper's zeroth-order gradient, not the
+exact derivative of the piecewise-constant propagation: the two differ by
+O(dt) relative, so torch.autograd.gradcheck does not apply to it; it is checked
 against the oracle's zeroth-order gradient and, through finite differences of
-the forward, against the exact piecewise-constant gradient within O(dt).
+the forward, against the exact piecewise-constant gradient within O(dt).  The
+quadrature mode (nodes > 0) is the exact derivative to the accuracy of the rule
+and passes gradcheck.
 """
 
 from __future__ import annotations
@@ -31,11 +35,13 @@ class GrapeFidelity(torch.autograd.Function):
     @staticmethod
     def forward(ctx, u: torch.Tensor, h: XXZ, dt: float, k: Krylov, psi0: torch.Tensor,
                 target: torch.Tensor, ckpt_every: int = 0,
-                workspace: Optional[Workspace] = None, centred: bool = False):
+                workspace: Optional[Workspace] = None, centred: bool = False, nodes: int = 0):
         u = u.detach().contiguous()
-        ws = workspace if workspace is not None else Workspace(h, k, psi0.dtype, psi0.device)
+        ws = workspace if workspace is not None else Workspace(h, k, psi0.dtype, psi0.device,
+                                                                quadrature=nodes > 0)
         r = grape_forward(h, u, dt, k, psi0, target, ckpt_every=ckpt_every, workspace=ws)
         ctx.h, ctx.dt, ctx.k, ctx.ckpt_every, ctx.centred = h, dt, k, ckpt_every, centred
+        ctx.nodes = nodes
         ctx.psi0, ctx.target, ctx.ws = psi0, target, ws
         ctx.states, ctx.beta = r.states, r.beta
         ctx.save_for_backward(u)
@@ -46,15 +52,19 @@ class GrapeFidelity(torch.autograd.Function):
         (u,) = ctx.saved_tensors
         r = grape_gradient(ctx.h, u, ctx.dt, ctx.k, ctx.psi0, ctx.target,
                            ckpt_every=ctx.ckpt_every, states=ctx.states, states_valid=True,
-                           beta=ctx.beta, workspace=ctx.ws, centred=ctx.centred)
+                           beta=ctx.beta, workspace=ctx.ws, centred=ctx.centred,
+                           nodes=ctx.nodes)
         grad_u = r.grad * gF.to(r.grad.dtype)
-        ctx.states = None
-        return grad_u, None, None, None, None, None, None, None, None
+        # the states stay with the graph: backward may run again on it
+        # (retain_graph, gradcheck's reentrancy check)
+        return grad_u, None, None, None, None, None, None, None, None, None
 
 
 def fidelity(u: torch.Tensor, h: XXZ, dt: float, k: Krylov, psi0: torch.Tensor,
              target: torch.Tensor, ckpt_every: int = 0,
-             workspace: Optional[Workspace] = None, centred: bool = False) -> torch.Tensor:
+             workspace: Optional[Workspace] = None, centred: bool = False,
+             nodes: int = 0) -> torch.Tensor:
     """Differentiable fidelity; u is a float64 device tensor of N controls.  The
-    backward gives the zeroth-order gradient, or its centred variant."""
-    return GrapeFidelity.apply(u, h, dt, k, psi0, target, ckpt_every, workspace, centred)
+    backward gives the zeroth-order gradient, its centred variant, or (nodes > 0)
+    the exact gradient by in-slice quadrature."""
+    return GrapeFidelity.apply(u, h, dt, k, psi0, target, ckpt_every, workspace, centred, nodes)

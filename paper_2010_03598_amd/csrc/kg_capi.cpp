@@ -158,6 +158,8 @@ kg_status carve(void* ws, size_t ws_bytes, const kg_xxz* h, const kg_krylov* k, 
     q += align_up(vec_bytes(h->L, prec) * (size_t)(k->m - 1), 256);
     o->hx = q;
     o->lam = p + 2 * slot_bytes(h, k, prec);
+    o->node_a = nullptr;
+    o->node_b = nullptr;
   }
   return KG_OK;
 }
@@ -246,11 +248,21 @@ kg_status forward_sweep(const SweepArgs& a, const States& S, double* F_dev, doub
   return KG_OK;
 }
 
+// Nodes of the in-slice quadrature: times s_q in (0, dt) and weights w_q.
+struct Quadrature {
+  int n = 0;
+  double s[KG_MAX_NODES];
+  double w[KG_MAX_NODES];
+};
+
 // Costate sweep and brackets.  With `centred`, the sweep continues to
 // lambda_0 = U_1^dagger lambda_1, takes the bracket with psi_0 into KState::g0
 // and replaces every g_j by the mean of the brackets at the two ends of slice j.
+// With a quadrature (Q.n > 0), slice j's entry is instead
+//   sum_q 2 w_q Im(conj(beta) <e^{+iH_j(dt-s_q)} lambda_j| Hc |e^{-iH_j s_q} psi_{j-1}>),
+// the node states coming from paired Krylov calls on the two workspace slots.
 kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta_dev,
-                         double* grad_dev, bool centred = false) {
+                         double* grad_dev, bool centred = false, const Quadrature* Q = nullptr) {
   const HvArgs hc = make_hv(a.h, nullptr, 0.0);
   const void* lam = a.target;
   for (int q = S.nseg - 1; q >= 0; --q) {
@@ -263,12 +275,23 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
     const void* re_in = recompute ? (rq == 0 ? a.psi0 : S.ckpt(rq)) : nullptr;
     int re_i = 1;
     for (int j = cs + len; j > cs; --j) {
-      Profiler* prof = profiler_for_launch();
-      if (prof) profiler_start(prof, a.stream);
-      KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.at(j), a.dt, beta_dev, a.ws,
-                            grad_dev + (j - 1), a.stream),
-             "gradient bracket");
-      if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * vec_bytes(a.h->L, a.prec));
+      if (Q && Q->n > 0) {
+        for (int q = 0; q < Q->n; ++q) {
+          const KrylovCall ca = krylov_call(a, j, Q->s[q], S.at0(j - 1), a.ws.node_a);
+          const KrylovCall cb = krylov_call(a, j, -(a.dt - Q->s[q]), lam, a.ws.node_b);
+          KG_HIP(launch_krylov_pair(ca, a.ws, cb, a.ws1, a.stream), "quadrature node states");
+          KG_HIP(launch_bracket(a.prec, hc, a.geo.D, a.ws.node_b, a.ws.node_a, Q->w[q], beta_dev,
+                                a.ws, grad_dev + (j - 1), a.stream, q > 0),
+                 "quadrature bracket");
+        }
+      } else {
+        Profiler* prof = profiler_for_launch();
+        if (prof) profiler_start(prof, a.stream);
+        KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.at(j), a.dt, beta_dev, a.ws,
+                              grad_dev + (j - 1), a.stream),
+               "gradient bracket");
+        if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * vec_bytes(a.h->L, a.prec));
+      }
       if (j > 1 || centred) {
         const KrylovCall cb = krylov_call(a, j, -a.dt, lam, a.ws.lam);
         if (recompute && re_i <= S.c - 1) {
@@ -508,20 +531,55 @@ kg_status gradient_impl(const kg_xxz* h, const double* u_dev, int32_t N, double 
                         const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
                         double* F_dev, double* beta_dev, double* grad_dev, void* states,
                         int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
-                        void* stream, bool centred, const char* name) {
+                        void* stream, bool centred, const char* name,
+                        const Quadrature* Q = nullptr) {
   KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
   if (!beta_dev || !grad_dev) return fail(KG_EINVAL, "beta_dev and grad_dev are required");
   if (states_valid != 0 && states_valid != 1) return fail(KG_EINVAL, "states_valid must be 0 or 1");
   Workspace W, W1;
   KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, &W1));
+  if (Q) {
+    const size_t base = kg_workspace_bytes(h, k, prec);
+    const size_t need = kg_quadrature_workspace_bytes(h, k, prec);
+    if (ws_bytes < need)
+      return fail(KG_EWORKSPACE, "workspace has %zu bytes, the quadrature needs %zu", ws_bytes,
+                  need);
+    W.node_a = static_cast<char*>(ws) + base;
+    W.node_b = static_cast<char*>(W.node_a) + align_up(vec_bytes(h->L, prec), 256);
+  }
   SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
               make_geo(h->L, prec, tile_override_from_env()), W, W1, (hipStream_t)stream};
   const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
   KG_HIP(launch_init(W.st, a.stream), name);
   KG_HIP(launch_init(W1.st, a.stream), name);
   if (!states_valid) KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
-  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev, centred));
+  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev, centred, Q));
   return ok();
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's iteration on P_n
+// (three-term recurrence) from the starting values cos(pi (i + 3/4) / (n + 1/2)),
+// weights 2 / ((1 - x^2) P_n'(x)^2).
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int kk = 2; kk <= n; ++kk) {
+        const double p2 = ((2.0 * kk - 1.0) * z * p1 - (kk - 1.0) * p0) / kk;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(z), p0 = P_{n-1}(z) (P_0 = 1 when n = 1)
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (fabs(dz) <= 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
 }
 
 }  // namespace
@@ -533,6 +591,33 @@ kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double
                          void* stream) {
   return gradient_impl(h, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev, states,
                        ckpt_every, states_valid, ws, ws_bytes, stream, false, "grape_gradient");
+}
+
+size_t kg_quadrature_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
+  const size_t base = kg_workspace_bytes(h, k, prec);
+  if (!base) return 0;
+  return base + 2 * align_up(vec_bytes(h->L, prec), 256);
+}
+
+kg_status grape_gradient_quadrature(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                    const kg_krylov* k, int32_t prec, const void* psi0,
+                                    const void* target, double* F_dev, double* beta_dev,
+                                    double* grad_dev, void* states, int32_t ckpt_every,
+                                    int32_t states_valid, int32_t nodes, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (nodes < 1 || nodes > KG_MAX_NODES)
+    return fail(KG_EINVAL, "nodes=%d outside [1, %d]", nodes, KG_MAX_NODES);
+  Quadrature Q;
+  Q.n = nodes;
+  double x[KG_MAX_NODES], w[KG_MAX_NODES];
+  gauss_legendre(nodes, x, w);
+  for (int q = 0; q < nodes; ++q) {
+    Q.s[q] = 0.5 * dt * (x[q] + 1.0);
+    Q.w[q] = 0.5 * dt * w[q];
+  }
+  return gradient_impl(h, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev, states,
+                       ckpt_every, states_valid, ws, ws_bytes, stream, false,
+                       "grape_gradient_quadrature", &Q);
 }
 
 kg_status grape_gradient_centred(const kg_xxz* h, const double* u_dev, int32_t N, double dt,

@@ -70,6 +70,8 @@ struct Workspace {         // carved from the caller's workspace
   void* basis;             // m-1 vectors (stored Krylov vectors 1..m-1)
   void* hx;                // one vector: H v_k of the running basis step
   void* lam;               // one vector (costate)
+  void* node_a;            // quadrature workspaces only: psi at a node
+  void* node_b;            //   and lambda at the node
 };
 
 size_t ws_fixed_bytes();
@@ -108,7 +110,8 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
                           double* F_dev, double* beta_dev, hipStream_t s);
 hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
                           double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
-                          hipStream_t s);
+                          hipStream_t s,
+                          bool accumulate = false);
 hipError_t launch_init(KState* st, hipStream_t s);
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
 hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s);

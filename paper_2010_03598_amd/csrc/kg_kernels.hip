@@ -571,12 +571,13 @@ __global__ void __launch_bounds__(kStreamBlock)
   }
 }
 
-// g_j = 2 dt Im(conj(beta) <lambda|Hc|psi>)  (Eq. 5 with chi = beta lambda, sign of dF).
+// g_j = 2 dt Im(conj(beta) <lambda|Hc|psi>)  (Eq. 5 with chi = beta lambda, sign of dF),
+// written to *grad_slot, or added to it with `accumulate` (quadrature nodes).
 template <typename R>
 __global__ void __launch_bounds__(kStreamBlock)
     k_bracket(HvArgs a, uint32_t D, const typename VT<R>::T* __restrict__ lam,
               const typename VT<R>::T* __restrict__ psi, double dt, const double* beta_dev,
-              KState* st, cplx_d* partials, double* grad_slot) {
+              KState* st, cplx_d* partials, double* grad_slot, int accumulate) {
   using V = typename VT<R>::T;
   constexpr int E = RedChunk<R>::n;
   __shared__ cplx_d wacc[(kStreamBlock / 64) * kMaxScal];
@@ -614,7 +615,8 @@ __global__ void __launch_bounds__(kStreamBlock)
   if (threadIdx.x == 0) {
     const double br = beta_dev[0], bi = beta_dev[1];
     const cplx_d B = tot[0];
-    *grad_slot = 2.0 * dt * (br * B.im - bi * B.re);
+    const double g = 2.0 * dt * (br * B.im - bi * B.re);
+    *grad_slot = accumulate ? *grad_slot + g : g;
   }
 }
 
@@ -838,16 +840,17 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
 
 hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
                           double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
-                          hipStream_t s) {
+                          hipStream_t s, bool accumulate) {
   const int grid = reduce_grid(D, prec);
+  const int acc = accumulate ? 1 : 0;
   if (prec == 0) {
     hipLaunchKernelGGL(k_bracket<double>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const double2*>(lam), reinterpret_cast<const double2*>(psi),
-                       dt, beta_dev, ws.st, ws.partials, grad_slot);
+                       dt, beta_dev, ws.st, ws.partials, grad_slot, acc);
   } else {
     hipLaunchKernelGGL(k_bracket<float>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const float2*>(lam), reinterpret_cast<const float2*>(psi),
-                       dt, beta_dev, ws.st, ws.partials, grad_slot);
+                       dt, beta_dev, ws.st, ws.partials, grad_slot, acc);
   }
   return hipGetLastError();
 }

@@ -1,0 +1,107 @@
+"""The exact piecewise-constant gradient by in-slice Gauss-Legendre quadrature
+(grape_gradient_quadrature) against the oracle's quadrature and the dense exact
+gradient; checkpointing; torch.autograd.gradcheck of the differentiable fidelity."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2010_03598_amd as kg
+from paper_2010_03598_amd import _lib, api
+import workloads
+from oracle import exact, krylov, model
+from oracle.model import HC_SX
+from tests.gpu_util import C64, C128, dev_vec, host, rel_err, xxz_of
+
+pytestmark = pytest.mark.gpu
+
+
+def chain(seed, L=7, N=9, m=14, dt=0.12):
+    rng = np.random.default_rng(seed)
+    return workloads.Chain(L=L, J=1.0, Delta=0.6, hc_kind=HC_SX, hc_sites=1 << 2, N=N, dt=dt, m=m,
+                           u=rng.uniform(-1, 1, N), psi0=workloads.random_state(rng, 1 << L),
+                           target=workloads.random_state(rng, 1 << L))
+
+
+def gpu(c, nodes, dtype=C128, ckpt_every=0):
+    r = kg.grape_gradient(xxz_of(c), torch.tensor(c.u, dtype=torch.float64, device="cuda"), c.dt,
+                          kg.Krylov(c.m), dev_vec(c.psi0, dtype), dev_vec(c.target, dtype),
+                          ckpt_every=ckpt_every, nodes=nodes)
+    torch.cuda.synchronize()
+    return r
+
+
+@pytest.mark.parametrize("nodes", [1, 3, 8])
+def test_vs_oracle_quadrature(nodes):
+    c = chain(1)
+    ch = model.Chain(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    F, gq = exact.exact_gradient_quadrature(ch, c.u, c.psi0, c.target, c.dt, c.m, nodes=nodes)
+    ref = np.array([gq[j] for j in range(c.N)])
+    r = gpu(c, nodes)
+    assert abs(float(host(r.F)) - F) / F <= 1e-10
+    assert rel_err(host(r.grad), ref) <= 1e-10
+    r64 = gpu(c, nodes, C64)
+    assert rel_err(host(r64.grad), ref) <= 1e-4
+
+
+def test_vs_dense_exact_gradient():
+    """Six nodes make the rule exact to rounding for these slices: the GPU gradient
+    equals the dense Daleckii-Krein derivative of the piecewise-constant F."""
+    c = chain(2)
+    H0 = model.xxz_dense(c.L, c.J, c.Delta)
+    Hc = model.hc_dense(c.L, c.hc_kind, c.hc_sites)
+    _, g_exact = exact.exact_gradient_dense(H0, Hc, c.u, c.psi0, c.target, c.dt)
+    r = gpu(c, 6)
+    assert rel_err(host(r.grad), g_exact) <= 1e-10
+
+
+@pytest.mark.parametrize("ckpt", [1, 4, 9])
+def test_checkpointed_is_bit_identical(ckpt):
+    c = chain(3)
+    ref = host(gpu(c, 4).grad)
+    assert np.array_equal(host(gpu(c, 4, C128, ckpt).grad), ref)
+
+
+def test_gradcheck():
+    c = chain(4, L=6, N=5, m=16, dt=0.2)
+    h, k = xxz_of(c), kg.Krylov(c.m)
+    psi0, f = dev_vec(c.psi0), dev_vec(c.target)
+    u = torch.tensor(c.u, dtype=torch.float64, device="cuda", requires_grad=True)
+    fn = lambda uu: kg.fidelity(uu, h, c.dt, k, psi0, f, 0, None, False, 6)
+    assert torch.autograd.gradcheck(fn, (u,), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_workspace_size_checked():
+    """The plain workspace lacks the two node vectors: the call is refused."""
+    c = chain(5)
+    h, k = xxz_of(c), kg.Krylov(c.m)
+    small = kg.Workspace(h, k, C128)
+    dev = torch.device("cuda")
+    u = torch.tensor(c.u, device=dev)
+    F = torch.empty((), dtype=torch.float64, device=dev)
+    beta = torch.empty(2, dtype=torch.float64, device=dev)
+    g = torch.empty(c.N, dtype=torch.float64, device=dev)
+    st = kg.new_states(h, c.N, 0, C128)
+    status = _lib.load().grape_gradient_quadrature(
+        ctypes.byref(h.c()), api._ptr(u), c.N, c.dt, ctypes.byref(k.c()), _lib.KG_C128,
+        api._ptr(dev_vec(c.psi0)), api._ptr(dev_vec(c.target)), api._ptr(F), api._ptr(beta),
+        api._ptr(g), api._ptr(st), 0, 0, 4, small.ptr, small.nbytes, None)
+    assert status == _lib.KG_EWORKSPACE
+    big = kg.Workspace(h, k, C128, quadrature=True)
+    assert big.nbytes > small.nbytes
+
+
+def test_adjoint_chain_short_vs_oracle_exact_gradient():
+    """L=20 (D = 1,048,576), 8 slices: the GPU quadrature gradient against the
+    oracle's exact gradient stored in tests/golden (8-node quadrature)."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "adjoint_short.json")) as fh:
+        gold = json.load(fh)
+    c = workloads.adjoint(N=8)
+    r = gpu(c, 8)
+    g = host(r.grad)[gold["exact_grad_slices"]]
+    assert rel_err(g, np.array(gold["exact_grad"])) <= 1e-9
