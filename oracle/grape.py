@@ -105,6 +105,42 @@ def gradient_centred(chain: Chain, u, psi0, target, dt, m, reorth=True, tol=None
                       m_eff_bwd=m_bwd)
 
 
+def gradient_hierarchy(chain: Chain, u, psi0, target, dt, m, P, reorth=True,
+                       tol=None) -> GradResult:
+    """Gradient from the truncated Taylor hierarchy of the time-averaged control
+    operator (App. B): Hc_bar^[P] = sum_{p=0}^{P} (-i dt)^p / (p+1)! L^p Hc with the
+    Liouvillian L = [H_j, .], and dF/du_j ~ 2 dt Im(conj(beta) <lambda_j|Hc_bar^[P]|psi_j>).
+    P = 0 is Eq. 5.  Matrix-free: <lambda|L^p Hc|psi> = sum_k C(p,k) (-1)^k
+    <H^(p-k) lambda| Hc |H^k psi> for Hermitian H."""
+    from math import comb, factorial
+    u = np.asarray(u, dtype=np.float64)
+    N = u.shape[0]
+    states, m_fwd = forward(chain, u, psi0, dt, m, reorth, tol, keep=True)
+    beta = overlap(target, states[N])
+    lam = np.asarray(target, dtype=np.complex128)
+    g = np.zeros(N)
+    m_bwd = np.zeros(N, dtype=np.int64)
+    for j in range(N, 0, -1):
+        uj = u[j - 1]
+        hp = [states[j]]                 # H^k psi_j
+        hl = [lam]                       # H^k lambda_j
+        for _ in range(P):
+            hp.append(chain.apply(uj, hp[-1]))
+            hl.append(chain.apply(uj, hl[-1]))
+        val = 0.0 + 0.0j
+        for p in range(P + 1):
+            lp = sum(comb(p, k) * (-1) ** k * np.vdot(hl[p - k], chain.apply_hc(hp[k]))
+                     for k in range(p + 1))
+            val += (-1j * dt) ** p / factorial(p + 1) * lp
+        g[j - 1] = 2.0 * dt * (np.conj(beta) * val).imag
+        if j > 1:
+            lam, lz = krylov.expv(lambda v, uj=uj: chain.apply(uj, v), lam, -dt, m, reorth, tol,
+                                  return_info=True)
+            m_bwd[j - 1] = lz.m_eff
+    return GradResult(F=abs(beta) ** 2, beta=beta, grad=g, psi_N=states[N], m_eff_fwd=m_fwd,
+                      m_eff_bwd=m_bwd)
+
+
 def ascent_update(u, g, eta):
     """u + eta * g / max|g| (no change when the gradient vanishes)."""
     gmax = float(np.max(np.abs(g)))
