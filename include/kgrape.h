@@ -14,6 +14,8 @@
  *                   (the centred variant of App. B, error O(dt^3) per slice)
  *   grape_gradient_quadrature  exact piecewise-constant gradient by Gauss-Legendre
  *                   quadrature of the natural gradient inside each slice (App. B)
+ *   grape_gradient_first_order  first order of the hierarchy of the time-averaged
+ *                   control operator (one commutator with H_j, App. B)
  *   grape_ascent_update  u <- u + eta g / max|g|            (steepest ascent, Algorithm 1 update)
  *
  * Model.  Open chain of L spins 1/2, S = sigma/2:
@@ -187,16 +189,32 @@ kg_status grape_gradient_centred(const kg_xxz* h, const double* u_dev, int32_t N
  * Its error is that of the n-point rule, O(dt^(2n+1)) per slice, plus the
  * Krylov error, so it is the derivative of the forward's F to that accuracy.
  * nodes: 1..KG_MAX_NODES.  The workspace must hold
- * kg_quadrature_workspace_bytes (two node vectors beyond kg_workspace_bytes).
+ * kg_extended_workspace_bytes (two node vectors beyond kg_workspace_bytes).
  * Other arguments, buffers and errors as grape_gradient. */
 #define KG_MAX_NODES 16
-size_t kg_quadrature_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec);
+/* Workspace of grape_gradient_quadrature and grape_gradient_first_order:
+ * kg_workspace_bytes plus two vectors.  Returns 0 for invalid arguments. */
+size_t kg_extended_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec);
 kg_status grape_gradient_quadrature(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
                                     const kg_krylov* k, int32_t prec, const void* psi0,
                                     const void* target, double* F_dev, double* beta_dev,
                                     double* grad_dev, void* states, int32_t ckpt_every,
                                     int32_t states_valid, int32_t nodes, void* ws,
                                     size_t ws_bytes, void* stream);
+
+/* First order of the Taylor hierarchy of the time-averaged control operator
+ * (App. B): Hc_bar^[1] = Hc - (i dt / 2) [H_j, Hc], and
+ *   dF/du_j ~ 2 dt Im(conj(beta) <lambda_j| Hc_bar^[1] |psi_j>)
+ *           = 2 dt Im(conj(beta) (<lambda|Hc psi> - (i dt/2)(<H lambda|Hc psi> - <lambda|Hc H psi>))),
+ * two H v products per slice beyond Eq. 5.  Error O(dt^3) per slice.  The
+ * workspace must hold kg_extended_workspace_bytes; other arguments as
+ * grape_gradient. */
+kg_status grape_gradient_first_order(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                     const kg_krylov* k, int32_t prec, const void* psi0,
+                                     const void* target, double* F_dev, double* beta_dev,
+                                     double* grad_dev, void* states, int32_t ckpt_every,
+                                     int32_t states_valid, void* ws, size_t ws_bytes,
+                                     void* stream);
 
 /* Steepest-ascent update u_j <- u_j + eta * g_j / max_i |g_i| on the device
  * (u unchanged when g = 0).  N >= 1.  Errors: KG_EINVAL, KG_EDEVICE. */

@@ -65,7 +65,7 @@ SIGNATURES = {
     "kg_last_error": (ctypes.c_char_p, []),
     "kg_version": (_I32, []),
     "kg_workspace_bytes": (_SZ, [_PX, _PK, _I32]),
-    "kg_quadrature_workspace_bytes": (_SZ, [_PX, _PK, _I32]),
+    "kg_extended_workspace_bytes": (_SZ, [_PX, _PK, _I32]),
     "kg_states_bytes": (_SZ, [_PX, _I32, _I32, _I32]),
     "xxz_apply": (_I32, [_PX, _D, _I32, _P, _P, _P]),
     "krylov_expv": (_I32, [_PX, _D, _D, _PK, _I32, _P, _P, _P, _SZ, _P, _P]),
@@ -76,6 +76,8 @@ SIGNATURES = {
                                       _I32, _P, _SZ, _P]),
     "grape_gradient_quadrature": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _P,
                                          _I32, _I32, _I32, _P, _SZ, _P]),
+    "grape_gradient_first_order": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _P,
+                                          _I32, _I32, _P, _SZ, _P]),
     "grape_ascent_update": (_I32, [_P, _P, _I32, _D, _P]),
     "kg_debug_index_map": (_I32, [_I32, _U32, _U32, _P, _P, _P]),
     "kg_profile_begin": (_I32, [_I32, _I32]),

@@ -84,18 +84,18 @@ def _f64(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
     return t
 
 
-def _ws_bytes(h: XXZ, k: Krylov, dtype: torch.dtype, quadrature: bool) -> int:
-    fn = "kg_quadrature_workspace_bytes" if quadrature else "kg_workspace_bytes"
+def _ws_bytes(h: XXZ, k: Krylov, dtype: torch.dtype, extended: bool) -> int:
+    fn = "kg_extended_workspace_bytes" if extended else "kg_workspace_bytes"
     return int(getattr(_lib.load(), fn)(ctypes.byref(h.c()), ctypes.byref(k.c()), prec_of(dtype)))
 
 
 class Workspace:
     """Device scratch for krylov_expv / grape_forward / grape_gradient (with
-    `quadrature`, large enough for the quadrature gradient as well)."""
+    `extended`, large enough for the quadrature and first-order gradients too)."""
 
     def __init__(self, h: XXZ, k: Krylov, dtype: torch.dtype, device=None,
-                 quadrature: bool = False):
-        self.nbytes = _ws_bytes(h, k, dtype, quadrature)
+                 extended: bool = False):
+        self.nbytes = _ws_bytes(h, k, dtype, extended)
         if self.nbytes == 0:
             raise ValueError(_lib.last_error() or "invalid chain or Krylov options")
         self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8,
@@ -103,8 +103,8 @@ class Workspace:
         off = (-self.buf.data_ptr()) % 256
         self.ptr = ctypes.c_void_p(self.buf.data_ptr() + off)
 
-    def fits(self, h: XXZ, k: Krylov, dtype: torch.dtype, quadrature: bool = False) -> bool:
-        need = _ws_bytes(h, k, dtype, quadrature)
+    def fits(self, h: XXZ, k: Krylov, dtype: torch.dtype, extended: bool = False) -> bool:
+        need = _ws_bytes(h, k, dtype, extended)
         return need != 0 and need <= self.nbytes
 
 
@@ -123,9 +123,9 @@ def new_states(h: XXZ, N: int, ckpt_every: int, dtype: torch.dtype, device=None)
 
 
 def _ws(ws: Optional[Workspace], h: XXZ, k: Krylov, dtype, device,
-        quadrature: bool = False) -> Workspace:
-    if ws is None or not ws.fits(h, k, dtype, quadrature):
-        ws = Workspace(h, k, dtype, device, quadrature)
+        extended: bool = False) -> Workspace:
+    if ws is None or not ws.fits(h, k, dtype, extended):
+        ws = Workspace(h, k, dtype, device, extended)
     return ws
 
 
@@ -189,15 +189,16 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
                    states_valid: bool = False, beta: Optional[torch.Tensor] = None,
                    grad: Optional[torch.Tensor] = None, F: Optional[torch.Tensor] = None,
                    workspace: Optional[Workspace] = None, centred: bool = False,
-                   nodes: int = 0) -> GrapeResult:
+                   nodes: int = 0, first_order: bool = False) -> GrapeResult:
     """Fidelity and gradient dF/du_j: the zeroth-order gradient of Eq. 5; with
     `centred` its centred variant (the bracket at both ends of each slice,
     averaged; App. B); with `nodes` > 0 the exact piecewise-constant gradient by
-    `nodes`-point Gauss-Legendre quadrature inside each slice.  With
-    states_valid, `states` and `beta` must come from grape_forward with the same
-    arguments."""
-    if centred and nodes:
-        raise ValueError("centred and nodes are exclusive")
+    `nodes`-point Gauss-Legendre quadrature inside each slice; with
+    `first_order` the first order of the hierarchy of the time-averaged control
+    operator (one commutator with H_j).  With states_valid, `states` and `beta`
+    must come from grape_forward with the same arguments."""
+    if int(bool(centred)) + int(bool(nodes)) + int(bool(first_order)) > 1:
+        raise ValueError("centred, nodes and first_order are exclusive")
     dtype = psi0.dtype
     _vec(psi0, h, dtype, "psi0")
     _vec(target, h, dtype, "target")
@@ -212,7 +213,7 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
         raise ValueError("states buffer too small")
     if states_valid and beta is None:
         raise ValueError("states_valid needs beta from grape_forward")
-    ws = _ws(workspace, h, k, dtype, dev, quadrature=nodes > 0)
+    ws = _ws(workspace, h, k, dtype, dev, extended=bool(nodes) or first_order)
     if F is None:
         F = torch.empty((), dtype=torch.float64, device=dev)
     if beta is None:
@@ -226,6 +227,8 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
     if nodes:
         name = "grape_gradient_quadrature"
         args.append(int(nodes))
+    elif first_order:
+        name = "grape_gradient_first_order"
     else:
         name = "grape_gradient_centred" if centred else "grape_gradient"
     _lib.check(name, getattr(_lib.load(), name)(*args, ws.ptr, ws.nbytes, _stream()))

@@ -38,7 +38,7 @@ class GrapeFidelity(torch.autograd.Function):
                 workspace: Optional[Workspace] = None, centred: bool = False, nodes: int = 0):
         u = u.detach().contiguous()
         ws = workspace if workspace is not None else Workspace(h, k, psi0.dtype, psi0.device,
-                                                                quadrature=nodes > 0)
+                                                                extended=nodes > 0)
         r = grape_forward(h, u, dt, k, psi0, target, ckpt_every=ckpt_every, workspace=ws)
         ctx.h, ctx.dt, ctx.k, ctx.ckpt_every, ctx.centred = h, dt, k, ckpt_every, centred
         ctx.nodes = nodes

@@ -261,8 +261,11 @@ struct Quadrature {
 // With a quadrature (Q.n > 0), slice j's entry is instead
 //   sum_q 2 w_q Im(conj(beta) <e^{+iH_j(dt-s_q)} lambda_j| Hc |e^{-iH_j s_q} psi_{j-1}>),
 // the node states coming from paired Krylov calls on the two workspace slots.
+// With `first_order`, the bracket takes Hc - (i dt/2)[H_j, Hc]: H_j psi_j and
+// H_j lambda_j go to the node vectors and two more brackets are added.
 kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta_dev,
-                         double* grad_dev, bool centred = false, const Quadrature* Q = nullptr) {
+                         double* grad_dev, bool centred = false, const Quadrature* Q = nullptr,
+                         bool first_order = false) {
   const HvArgs hc = make_hv(a.h, nullptr, 0.0);
   const void* lam = a.target;
   for (int q = S.nseg - 1; q >= 0; --q) {
@@ -291,6 +294,19 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
                               grad_dev + (j - 1), a.stream),
                "gradient bracket");
         if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * vec_bytes(a.h->L, a.prec));
+        if (first_order) {
+          const HvArgs hj = make_hv(a.h, a.u_dev + (j - 1), 0.0);
+          const double c1 = 0.5 * a.dt * a.dt;
+          KG_HIP(launch_hv(a.prec, hj, a.geo, S.at(j), a.ws.node_a, a.stream), "H psi_j");
+          KG_HIP(launch_hv(a.prec, hj, a.geo, lam, a.ws.node_b, a.stream), "H lambda_j");
+          // - (i dt^2/2) <H lambda|Hc psi> + (i dt^2/2) <lambda|Hc H psi>
+          KG_HIP(launch_bracket(a.prec, hc, a.geo.D, a.ws.node_b, S.at(j), 0.0, beta_dev, a.ws,
+                                grad_dev + (j - 1), a.stream, true, -c1),
+                 "first-order bracket");
+          KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, a.ws.node_a, 0.0, beta_dev, a.ws,
+                                grad_dev + (j - 1), a.stream, true, c1),
+                 "first-order bracket");
+        }
       }
       if (j > 1 || centred) {
         const KrylovCall cb = krylov_call(a, j, -a.dt, lam, a.ws.lam);
@@ -532,18 +548,17 @@ kg_status gradient_impl(const kg_xxz* h, const double* u_dev, int32_t N, double 
                         double* F_dev, double* beta_dev, double* grad_dev, void* states,
                         int32_t ckpt_every, int32_t states_valid, void* ws, size_t ws_bytes,
                         void* stream, bool centred, const char* name,
-                        const Quadrature* Q = nullptr) {
+                        const Quadrature* Q = nullptr, bool first_order = false) {
   KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
   if (!beta_dev || !grad_dev) return fail(KG_EINVAL, "beta_dev and grad_dev are required");
   if (states_valid != 0 && states_valid != 1) return fail(KG_EINVAL, "states_valid must be 0 or 1");
   Workspace W, W1;
   KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, &W1));
-  if (Q) {
+  if (Q || first_order) {
     const size_t base = kg_workspace_bytes(h, k, prec);
-    const size_t need = kg_quadrature_workspace_bytes(h, k, prec);
+    const size_t need = kg_extended_workspace_bytes(h, k, prec);
     if (ws_bytes < need)
-      return fail(KG_EWORKSPACE, "workspace has %zu bytes, the quadrature needs %zu", ws_bytes,
-                  need);
+      return fail(KG_EWORKSPACE, "workspace has %zu bytes, %s needs %zu", ws_bytes, name, need);
     W.node_a = static_cast<char*>(ws) + base;
     W.node_b = static_cast<char*>(W.node_a) + align_up(vec_bytes(h->L, prec), 256);
   }
@@ -553,7 +568,7 @@ kg_status gradient_impl(const kg_xxz* h, const double* u_dev, int32_t N, double 
   KG_HIP(launch_init(W.st, a.stream), name);
   KG_HIP(launch_init(W1.st, a.stream), name);
   if (!states_valid) KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
-  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev, centred, Q));
+  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev, centred, Q, first_order));
   return ok();
 }
 
@@ -593,7 +608,7 @@ kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double
                        ckpt_every, states_valid, ws, ws_bytes, stream, false, "grape_gradient");
 }
 
-size_t kg_quadrature_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
+size_t kg_extended_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
   const size_t base = kg_workspace_bytes(h, k, prec);
   if (!base) return 0;
   return base + 2 * align_up(vec_bytes(h->L, prec), 256);
@@ -618,6 +633,17 @@ kg_status grape_gradient_quadrature(const kg_xxz* h, const double* u_dev, int32_
   return gradient_impl(h, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev, states,
                        ckpt_every, states_valid, ws, ws_bytes, stream, false,
                        "grape_gradient_quadrature", &Q);
+}
+
+kg_status grape_gradient_first_order(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                     const kg_krylov* k, int32_t prec, const void* psi0,
+                                     const void* target, double* F_dev, double* beta_dev,
+                                     double* grad_dev, void* states, int32_t ckpt_every,
+                                     int32_t states_valid, void* ws, size_t ws_bytes,
+                                     void* stream) {
+  return gradient_impl(h, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev, states,
+                       ckpt_every, states_valid, ws, ws_bytes, stream, false,
+                       "grape_gradient_first_order", nullptr, true);
 }
 
 kg_status grape_gradient_centred(const kg_xxz* h, const double* u_dev, int32_t N, double dt,

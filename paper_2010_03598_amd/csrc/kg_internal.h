@@ -110,8 +110,7 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
                           double* F_dev, double* beta_dev, hipStream_t s);
 hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
                           double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
-                          hipStream_t s,
-                          bool accumulate = false);
+                          hipStream_t s, bool accumulate = false, double coef_im = 0.0);
 hipError_t launch_init(KState* st, hipStream_t s);
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
 hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s);

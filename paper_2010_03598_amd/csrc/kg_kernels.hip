@@ -571,13 +571,15 @@ __global__ void __launch_bounds__(kStreamBlock)
   }
 }
 
-// g_j = 2 dt Im(conj(beta) <lambda|Hc|psi>)  (Eq. 5 with chi = beta lambda, sign of dF),
-// written to *grad_slot, or added to it with `accumulate` (quadrature nodes).
+// g_j = 2 Im(conj(beta) c <lambda|Hc|psi>) with c = (cr, ci); c = dt gives Eq. 5
+// (chi = beta lambda, sign of dF).  Written to *grad_slot, or added to it with
+// `accumulate` (quadrature nodes, hierarchy terms).
 template <typename R>
 __global__ void __launch_bounds__(kStreamBlock)
     k_bracket(HvArgs a, uint32_t D, const typename VT<R>::T* __restrict__ lam,
-              const typename VT<R>::T* __restrict__ psi, double dt, const double* beta_dev,
-              KState* st, cplx_d* partials, double* grad_slot, int accumulate) {
+              const typename VT<R>::T* __restrict__ psi, double cr, double ci,
+              const double* beta_dev, KState* st, cplx_d* partials, double* grad_slot,
+              int accumulate) {
   using V = typename VT<R>::T;
   constexpr int E = RedChunk<R>::n;
   __shared__ cplx_d wacc[(kStreamBlock / 64) * kMaxScal];
@@ -615,7 +617,13 @@ __global__ void __launch_bounds__(kStreamBlock)
   if (threadIdx.x == 0) {
     const double br = beta_dev[0], bi = beta_dev[1];
     const cplx_d B = tot[0];
-    const double g = 2.0 * dt * (br * B.im - bi * B.re);
+    double g;
+    if (ci == 0.0) {
+      g = 2.0 * cr * (br * B.im - bi * B.re);
+    } else {
+      const double zr = cr * B.re - ci * B.im, zi = cr * B.im + ci * B.re;
+      g = 2.0 * (br * zi - bi * zr);
+    }
     *grad_slot = accumulate ? *grad_slot + g : g;
   }
 }
@@ -840,17 +848,17 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
 
 hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
                           double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
-                          hipStream_t s, bool accumulate) {
+                          hipStream_t s, bool accumulate, double coef_im) {
   const int grid = reduce_grid(D, prec);
   const int acc = accumulate ? 1 : 0;
   if (prec == 0) {
     hipLaunchKernelGGL(k_bracket<double>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const double2*>(lam), reinterpret_cast<const double2*>(psi),
-                       dt, beta_dev, ws.st, ws.partials, grad_slot, acc);
+                       dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc);
   } else {
     hipLaunchKernelGGL(k_bracket<float>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const float2*>(lam), reinterpret_cast<const float2*>(psi),
-                       dt, beta_dev, ws.st, ws.partials, grad_slot, acc);
+                       dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc);
   }
   return hipGetLastError();
 }

@@ -89,7 +89,7 @@ def test_workspace_size_checked():
         api._ptr(dev_vec(c.psi0)), api._ptr(dev_vec(c.target)), api._ptr(F), api._ptr(beta),
         api._ptr(g), api._ptr(st), 0, 0, 4, small.ptr, small.nbytes, None)
     assert status == _lib.KG_EWORKSPACE
-    big = kg.Workspace(h, k, C128, quadrature=True)
+    big = kg.Workspace(h, k, C128, extended=True)
     assert big.nbytes > small.nbytes
 
 
