@@ -251,8 +251,11 @@ __device__ void tri_exp_wave(double a, double lo, double hi, double t, double& c
     double tr = yr, ti = yi, ar = yr, ai = yi;
 #pragma unroll 4
     for (int p = 1; p <= 16; ++p) {
-      const double dr = __shfl_up(tr, 1, 64), di = __shfl_up(ti, 1, 64);
-      const double ur = __shfl_down(tr, 1, 64), ui = __shfl_down(ti, 1, 64);
+      // neighbours by DPP wavefront shifts: lane i reads lane i-1 (wave_shr:1)
+      // and lane i+1 (wave_shl:1); the lanes at the ends read 0, where the
+      // matching off-diagonal entry is 0 anyway
+      const double dr = dpp_f64<0x138>(tr), di = dpp_f64<0x138>(ti);
+      const double ur = dpp_f64<0x130>(tr), ui = dpp_f64<0x130>(ti);
       const double zr = a * tr + lo * dr + hi * ur;
       const double zi = a * ti + lo * di + hi * ui;
       const double c = tau / (double)p;
