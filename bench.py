@@ -115,6 +115,53 @@ def time_hv(kg, torch, L, dtype, reps=50):
             "launches": reps, "timing": "HIP graph of the launches, best of 3 replays"}
 
 
+def time_batched(kg, torch, workloads, steps=3, fp64=True):
+    """The batched form on the 64-chain workload (L in 10..16, N in 50..300): the
+    autotuned persistent launch (complex64 vectors, FP64 scalars; m per chain from
+    the a-priori error bound), timed over `steps` launches, against the FP64 path
+    run chain by chain with the same m (the batched kernel has no complex128
+    form)."""
+    import numpy as np
+    from paper_2010_03598_amd import batched
+    wl = workloads.batched()
+    chains = batched.from_workload(wl)
+    b, info = batched.autotune(chains, caps=(1, 2, 4, 8, 16))
+    b.gradient()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.gradient()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    b.check_status()
+    out = {"chains": len(chains), "value": len(chains) / sec, "unit": "chain gradient evals/s",
+           "ms_per_launch": sec * 1e3, "launches": steps, "team_cap": info["best_cap"],
+           "m": sorted({c.m for c in chains}), "element_slices": int(sum(c.N << c.h.L for c in chains))}
+    if fp64:
+        F32 = b.F.cpu().numpy()
+        errs_g, errs_F = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = []
+        for i, c in enumerate(chains):
+            r = kg.grape_gradient(c.h, c.u.to("cuda"), c.dt, kg.Krylov(c.m),
+                                  c.psi0.to(torch.complex128).to("cuda"),
+                                  c.target.to(torch.complex128).to("cuda"))
+            res.append(r)
+        torch.cuda.synchronize()
+        sec64 = time.perf_counter() - t0
+        for i, r in enumerate(res):
+            g64 = r.grad.cpu().numpy()
+            g32 = b.grad_of(i).cpu().numpy()
+            errs_g.append(float(np.linalg.norm(g32 - g64) / np.linalg.norm(g64)))
+            F64 = float(r.F.cpu())
+            errs_F.append(abs(float(F32[i]) - F64) / F64)
+        out["fp64_chain_by_chain"] = {"value": len(chains) / sec64, "unit": "chain gradient evals/s",
+                                      "seconds": sec64}
+        out["mixed_vs_fp64_error"] = {"grad_rel_l2_max": max(errs_g), "F_rel_max": max(errs_F)}
+    return out
+
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_a_L20_c64_traffic.md")
 KERNEL_OF_CLASS = {"pass_a": "k_pass_a", "pass_b": "k_pass_b", "combine": "k_combine"}
 
@@ -208,6 +255,7 @@ def main():
                     help="time every n-th Krylov call's kernels with HIP events (0: off)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -268,6 +316,9 @@ def main():
     hv24 = time_hv(kg, torch, 24, torch.complex64, reps=20)
     hv24_128 = time_hv(kg, torch, 24, torch.complex128, reps=20)
 
+    bat = None if args.no_batched else time_batched(kg, torch, workloads)
+    if bat:
+        log(f"batched: {bat['value']:.1f} chain gradient evals/s")
     cpu = None if args.no_cpu else cpu_baseline(c, args.cpu_budget)
 
     out = {
@@ -300,6 +351,7 @@ def main():
                      "avg_us": per_launch_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
                      "sampled_launches": d["launches"]},
         "kernels": classes,
+        "batched": bat,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
