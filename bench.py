@@ -125,7 +125,7 @@ def time_batched(kg, torch, workloads, steps=3, fp64=True):
     from paper_2010_03598_amd import batched
     wl = workloads.batched()
     chains = batched.from_workload(wl)
-    b, info = batched.autotune(chains, caps=(1, 2, 4, 8, 16))
+    b, info = batched.autotune(chains, caps=(2, 4, 8, 16, 32, 64))
     b.gradient()
     torch.cuda.synchronize()
     t0 = time.perf_counter()

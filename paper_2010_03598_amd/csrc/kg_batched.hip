@@ -10,10 +10,18 @@
 // member publishes its block totals, waits at the team barrier and adds the
 // members' totals in member order, so all members hold identical scalars and
 // no member ever waits for a single "last" block.  The barrier is an arrival
-// counter plus a generation word in global memory with device-scope fences; its
-// spin is bounded, and a timeout sets the status word, which makes every other
-// waiting member leave as well, so every wavefront of the launch terminates.
-// Teams of one workgroup synchronise with __syncthreads only.
+// counter plus a generation word in global memory; its spin is bounded, and a
+// timeout sets the status word, which makes every other waiting member leave as
+// well, so every wavefront of the launch terminates.  Teams of one workgroup
+// synchronise with __syncthreads only.
+//
+// Coherence without device-wide fences: every vector a member writes is stored
+// with device-scope (L2 write-through) stores, and every amplitude a member
+// reads from another member's tiles (H v partners, the S^x partner of a
+// bracket) and every reduction partial is loaded with device-scope loads.  A
+// member's own tiles are read with plain loads.  Before arriving at the
+// barrier a member waits for its stores to complete; no L2 is ever written
+// back or invalidated as a whole.
 
 #include <hip/hip_runtime.h>
 
@@ -40,7 +48,7 @@ struct TeamSync {
 };
 
 // Scratch of one chain at kg_chain::off_ws: sync word, two partial buffers,
-// the m-1 Krylov basis vectors and the costate vector.
+// the m-1 Krylov basis vectors, the costate vector and y = H v_k.
 __host__ __device__ inline size_t bws_partials_off() { return 256; }
 __host__ __device__ inline size_t bws_basis_off(int team) {
   const size_t p = 256 + 2 * (size_t)team * kMaxScal * sizeof(cplx_d);
@@ -57,22 +65,25 @@ struct BCtx {
   cplx_d* partials;   // [2][team][kMaxScal]
   float2* basis;
   float2* lam;
+  float2* ybuf;       // y = H v_k of the running step (own tiles only)
   int32_t* status;
 };
 
 __device__ bool team_barrier(BCtx& c) {
   __shared__ int ok;
   __syncthreads();
+  // every wavefront's stores are complete before the block is counted
+  complete_stores();
+  __syncthreads();
   if (threadIdx.x == 0) {
     int good = 1;
     if (c.team > 1) {
-      __threadfence();
       const uint32_t target = c.gen + 1;
       const uint32_t arrived =
           __hip_atomic_fetch_add(&c.sync->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
       if (arrived == c.team) {
         __hip_atomic_store(&c.sync->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
+        complete_stores();   // the reset lands before the new generation is seen
         __hip_atomic_store(&c.sync->gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else {
         uint32_t it = 0;
@@ -89,7 +100,7 @@ __device__ bool team_barrier(BCtx& c) {
           __builtin_amdgcn_s_sleep(4);
         }
       }
-      __threadfence();
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
       c.gen = target;
     }
     ok = good;
@@ -104,19 +115,24 @@ __device__ bool team_reduce(BCtx& c, cplx_d* tot, int ns) {
   cplx_d* buf = c.partials + (size_t)(c.red & 1u) * c.team * kMaxScal;
   c.red++;
   if (threadIdx.x < 64) {
-    for (int j = threadIdx.x; j < ns; j += 64) buf[(size_t)c.member * kMaxScal + j] = tot[j];
+    for (int j = threadIdx.x; j < ns; j += 64) {
+      st_agent(&buf[(size_t)c.member * kMaxScal + j].re, tot[j].re);
+      st_agent(&buf[(size_t)c.member * kMaxScal + j].im, tot[j].im);
+    }
   }
   if (!team_barrier(c)) return false;
+  // lane r takes member r's part (team <= 64); a fixed butterfly adds them, so
+  // every member obtains the same sums
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int j = wv; j < ns; j += nw) {
-    if (lane == 0) {
-      double re = 0.0, im = 0.0;
-      for (uint32_t r = 0; r < c.team; ++r) {
-        re += buf[(size_t)r * kMaxScal + j].re;
-        im += buf[(size_t)r * kMaxScal + j].im;
-      }
-      tot[j] = cplx_d{re, im};
+    double re = 0.0, im = 0.0;
+    if ((uint32_t)lane < c.team) {
+      re = ld_agent(&buf[(size_t)lane * kMaxScal + j].re);
+      im = ld_agent(&buf[(size_t)lane * kMaxScal + j].im);
     }
+    re = wave_sum(re);
+    im = wave_sum(im);
+    if (lane == 0) tot[j] = cplx_d{re, im};
   }
   __syncthreads();
   return true;
@@ -163,9 +179,10 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
     double acc_re = 0.0, acc_im = 0.0, acc_nn = 0.0;
     for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
       __syncthreads();
-      hv_tile<float, kBRB>(T, c.hv, c.geo, tile, x, lds, u, nullptr);
+      hv_tile<float, kBRB, true>(T, c.hv, c.geo, tile, x, lds, u, nullptr);
       const uint32_t s = (tile << kBTB) | lane | (wv << 6);
       const double yr = T.yr[0], yi = T.yi[0];
+      if (!last) c.ybuf[s] = V{T.yr[0], T.yi[0]};   // for pass B of this member
       for (int i = i0; i < k; i += 8) {
         V q[8];
 #pragma unroll
@@ -242,10 +259,10 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
     float2* vout = c.basis + (size_t)k * c.geo.D;
     double bnn = 0.0;
     for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
-      __syncthreads();
-      hv_tile<float, kBRB>(T, c.hv, c.geo, tile, x, lds, u, nullptr);
       const uint32_t s = (tile << kBTB) | lane | (wv << 6);
-      double zr = sk * (double)T.yr[0], zi = sk * (double)T.yi[0];
+      const V yv = c.ybuf[s];
+      const V xv = x[s];
+      double zr = sk * (double)yv.x, zi = sk * (double)yv.y;
       for (int i = i0; i < k; i += 8) {
         V q[8];
 #pragma unroll
@@ -262,13 +279,13 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
       }
       {
         const cplx_d cc = K.coef[k - i0];
-        zr -= cc.re * (double)T.xr[0] - cc.im * (double)T.xi[0];
-        zi -= cc.re * (double)T.xi[0] + cc.im * (double)T.xr[0];
+        zr -= cc.re * (double)xv.x - cc.im * (double)xv.y;
+        zi -= cc.re * (double)xv.y + cc.im * (double)xv.x;
       }
       V o;
       o.x = (float)zr;
       o.y = (float)zi;
-      vout[s] = o;
+      st_coh(&vout[s], o);      // read by other members as H v partners
       bnn += wave_sum((double)o.x * (double)o.x + (double)o.y * (double)o.y);
     }
     __syncthreads();
@@ -325,7 +342,7 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
     V o;
     o.x = (float)ar;
     o.y = (float)ai;
-    out[s] = o;
+    st_coh(&out[s], o);
   }
   return team_barrier(c);
 }
@@ -339,7 +356,7 @@ __device__ bool team_dot(BCtx& c, const float2* a, const float2* b, bool apply_h
   for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
     const uint32_t s = (tile << kBTB) | threadIdx.x;
     const float2 x = a[s];
-    const float2 y = b[s ^ flip];
+    const float2 y = flip ? ld_coh(&b[s ^ flip]) : b[s];   // the S^x partner may be another member's
     double w = 1.0;
     if (apply_hc) {
       w = (c.hv.hc_kind == 0) ? 0.5 : 0.5 * c.hv.sz_count - (double)__popc(s & c.hv.sz_mask);
@@ -390,6 +407,7 @@ __global__ void __launch_bounds__(kBThreads)
   c.basis = reinterpret_cast<float2*>(cw + bws_basis_off(ch.team_size));
   const uint32_t D = 1u << L;
   c.lam = c.basis + (size_t)(ch.m > 1 ? ch.m - 1 : 0) * D;
+  c.ybuf = c.lam + D;
   c.status = status;
   c.geo.L = L;
   c.geo.TB = kBTB;
@@ -469,7 +487,7 @@ __global__ void k_batched_init(const kg_chain* chains, int n_chains, char* ws, i
 
 size_t batched_chain_ws_bytes(int L, int m, int team) {
   const size_t vb = ((size_t)1 << L) * sizeof(float2);
-  return bws_basis_off(team) + vb * (size_t)(m > 1 ? m - 1 : 0) + vb;
+  return bws_basis_off(team) + vb * (size_t)(m > 1 ? m - 1 : 0) + 2 * vb;
 }
 
 hipError_t launch_batched(const kg_chain* chains_dev, int n_chains, int n_blocks, const double* u_all,

@@ -69,6 +69,43 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
 }
 
+// Vector element loads and stores that are coherent across the XCDs' L2
+// caches (device-scope atomics in 8-byte pieces): the channel through which
+// the workgroups of a team exchange amplitudes inside one launch.
+template <typename V>
+__device__ __forceinline__ V ld_coh(const V* p) {
+  static_assert(sizeof(V) == 8 || sizeof(V) == 16, "complex64 or complex128 amplitudes");
+  const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+  uint64_t b[sizeof(V) / 8];
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(V) / 8); ++i)
+    b[i] = __hip_atomic_load(q + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  V v;
+  __builtin_memcpy(&v, b, sizeof(V));
+  return v;
+}
+
+template <typename V>
+__device__ __forceinline__ void st_coh(V* p, const V& v) {
+  uint64_t b[sizeof(V) / 8];
+  __builtin_memcpy(b, &v, sizeof(V));
+  uint64_t* q = reinterpret_cast<uint64_t*>(p);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(V) / 8); ++i)
+    __hip_atomic_store(q + i, b[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A load of a partner amplitude: plain, or coherent when other workgroups of
+// the same launch wrote it (kCoh).
+template <bool kCoh, typename V>
+__device__ __forceinline__ V ld_partner(const V* p) {
+  if constexpr (kCoh) {
+    return ld_coh(p);
+  } else {
+    return *p;
+  }
+}
+
 __device__ __forceinline__ void st_agent_u32(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -320,10 +357,11 @@ __device__ __forceinline__ void next_far(uint32_t& glb, R hJ, uint32_t& flip, R&
 
 // y = (H0 + u Hc) x on one tile (amplitudes base .. base + 2^TB - 1).  The
 // tile's amplitudes, the S^x partners and the first far partners are requested
-// in one round trip before anything waits; when `done_flag` is set (a finished
+// in one round trip before anything waits (partners outside the tile with
+// coherent loads when kCoh: other workgroups of the launch wrote them); when `done_flag` is set (a finished
 // Krylov basis) the function returns false after issuing them, without
 // touching LDS, and the caller returns.
-template <typename R, int RB>
+template <typename R, int RB, bool kCoh = false>
 __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const Geo& g,
                                         uint32_t tile, const typename VT<R>::T* __restrict__ x,
                                         typename VT<R>::T* lds, double u,
@@ -379,7 +417,7 @@ __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
 #pragma unroll
-      for (int r = 0; r < NR; ++r) gq[j][r] = x[(base | eb | ((uint32_t)r << 6)) ^ f[j]];
+      for (int r = 0; r < NR; ++r) gq[j][r] = ld_partner<kCoh>(&x[(base | eb | ((uint32_t)r << 6)) ^ f[j]]);
     }
   }
   if (done_flag && *done_flag) return false;
@@ -426,7 +464,7 @@ __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const uint32_t e = eb | ((uint32_t)r << 6);
-      q[r] = (6 < TB) ? lds[e ^ flip] : x[(base | e) ^ flip];
+      q[r] = (6 < TB) ? lds[e ^ flip] : ld_partner<kCoh>(&x[(base | e) ^ flip]);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -470,7 +508,7 @@ __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
         for (int j = 0; j < NH; ++j) {
           const int r = j | (half << (RB - 1));
           const uint32_t e = eb | ((uint32_t)r << 6);
-          q[j] = in_lds ? lds[e ^ flip] : x[(base | e) ^ flip];
+          q[j] = in_lds ? lds[e ^ flip] : ld_partner<kCoh>(&x[(base | e) ^ flip]);
         }
 #pragma unroll
         for (int j = 0; j < NH; ++j) {
@@ -517,7 +555,7 @@ __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) gq[j][r] = x[(base | eb | ((uint32_t)r << 6)) ^ f[j]];
+        for (int r = 0; r < NR; ++r) gq[j][r] = ld_partner<kCoh>(&x[(base | eb | ((uint32_t)r << 6)) ^ f[j]]);
       }
 #pragma unroll
       for (int j = 0; j < NS; ++j) {
