@@ -64,11 +64,15 @@ def time_gradients(kg, torch, c, dtype, ckpt, steps, warmup, profile_every=0):
         torch.cuda.synchronize()
         log(f"warmup step {i + 1}/{warmup} done")
     prof = None
+    if profile_every:
+        # events are created here, outside the timed region; inside it only the
+        # sampled launches record events (about 2 * 40 * 1200 / profile_every
+        # launches per gradient evaluation)
+        prof = kg.profile(sample_every=profile_every,
+                          max_launches=max(1024, steps * 120000 // profile_every))
+        prof.__enter__()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    if profile_every:
-        prof = kg.profile(sample_every=profile_every, max_launches=1 << 20)
-        prof.__enter__()
     for i in range(steps):
         step()
     torch.cuda.synchronize()
