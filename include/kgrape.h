@@ -17,6 +17,9 @@
  *   grape_gradient_first_order  first order of the hierarchy of the time-averaged
  *                   control operator (one commutator with H_j, App. B)
  *   grape_ascent_update  u <- u + eta g / max|g|            (steepest ascent, Algorithm 1 update)
+ *   xxz_pe_apply, krylov_expv_pe, grape_forward_pe, grape_gradient_pe
+ *                   the same in the basis of fixed excitation number and even
+ *                   mirror parity (Sec. III.A), for S^z controls on mirror-symmetric sites
  *
  * Model.  Open chain of L spins 1/2, S = sigma/2:
  *   H0 = J sum_{i=1}^{L-1} (Sx_i Sx_{i+1} + Sy_i Sy_{i+1} + Delta Sz_i Sz_{i+1}).
@@ -220,6 +223,102 @@ kg_status grape_gradient_first_order(const kg_xxz* h, const double* u_dev, int32
  * (u unchanged when g = 0).  N >= 1.  Errors: KG_EINVAL, KG_EDEVICE. */
 kg_status grape_ascent_update(double* u_dev, const double* grad_dev, int32_t N, double eta,
                               void* stream);
+
+/* ---------------------------------------------------------------- reduced basis
+ * Sec. III.A: H0 and an S^z control on a mirror-symmetric set of sites conserve
+ * the number K of excitations (up spins, zero bits) and the mirror parity
+ * Pi: site i <-> L+1-i, so a state that starts in the even-parity part of the
+ * K-excitation sector stays there.  That part has one basis vector per orbit
+ * {s, Pi s} of the sector's patterns s: (|s> + |Pi s>)/sqrt(2), or |s> when
+ * Pi s = s.  Orbits are labelled by their smaller member and ordered by it
+ * (ascending binary number, up = 0, the ordering of Sec. III.A); kg_pe_dim
+ * gives their number, (C(L, K) + #palindromes) / 2.
+ *
+ * The _pe entry points take vectors of pe->dim amplitudes in this basis (same
+ * element types and alignment as the full-space calls) and compute exactly
+ * what their full-space counterparts compute on the embedded vectors: the
+ * reduced H v is y_b = d(r_b) x_b + (J/2) sum_p sqrt(n_b / n_a) x_a over the
+ * antiparallel bonds p of the label r_b (a the orbit of r_b with bits p, p+1
+ * exchanged, n the orbit sizes, d the diagonal of H0 + u Hc).  L may reach
+ * KG_PE_MAX_L here; the chain's control must be KG_HC_SZ with hc_sites
+ * mirror-symmetric (KG_EINVAL otherwise). */
+#define KG_PE_MAX_L 32
+
+/* A built reduced basis.  tables: device memory of kg_pe_tables_bytes,
+ * 256-byte aligned, owned by the caller and filled by kg_pe_build (binomial
+ * coefficients, orbit labels, the orbit index of every sector pattern by its
+ * combinatorial rank); it must stay allocated and unmodified while calls use it. */
+typedef struct kg_pe {
+  int32_t L;
+  int32_t K;
+  int64_t dim;
+  const void* tables;
+} kg_pe;
+
+/* Number of basis vectors for L spins and K excitations (0 for invalid
+ * arguments: 2 <= L <= KG_PE_MAX_L, 0 <= K <= L). */
+int64_t kg_pe_dim(int32_t L, int32_t K);
+
+/* Bytes of device tables of the basis (0 for invalid arguments). */
+size_t kg_pe_tables_bytes(int32_t L, int32_t K);
+
+/* The tables in HOST memory (no device call), kg_pe_tables_bytes long:
+ *   byte 0:          binomial coefficients C(n, k), uint32 at [n * 33 + k], n, k <= 32;
+ *   byte 4608:       the orbit labels, uint32, dim of them, ascending;
+ *   byte 4608 + R:   (R = 4 dim rounded up to a multiple of 256) the orbit
+ *                    index (int32) of every sector pattern s at its
+ *                    combinatorial rank sum_i C(z_i, i) over the zero-bit
+ *                    positions z_1 < z_2 < ... of s (C(L, K) entries).
+ * A caller may copy this image to device memory itself and fill a kg_pe with
+ * it.  Errors: KG_EINVAL, KG_EWORKSPACE. */
+kg_status kg_pe_tables_host(int32_t L, int32_t K, void* tables_host, size_t tables_bytes);
+
+/* kg_pe_tables_host into a host buffer, a synchronous host-to-device copy into
+ * tables_dev, and *pe filled.  Errors: KG_EINVAL, KG_EWORKSPACE (tables_bytes
+ * too small), KG_EDEVICE. */
+kg_status kg_pe_build(int32_t L, int32_t K, void* tables_dev, size_t tables_bytes, kg_pe* pe);
+
+/* Workspace bytes of krylov_expv_pe, grape_forward_pe and grape_gradient_pe:
+ * the layout of kg_workspace_bytes with vectors of pe->dim amplitudes;
+ * extended = 1 adds the two node vectors of the quadrature and first-order
+ * gradients.  0 for invalid arguments. */
+size_t kg_pe_workspace_bytes(const kg_pe* pe, const kg_krylov* k, int32_t prec, int32_t extended);
+
+/* Bytes of the forward-state buffer (layout of kg_states_bytes, vectors of
+ * pe->dim amplitudes).  0 for invalid arguments. */
+size_t kg_pe_states_bytes(const kg_pe* pe, int32_t N, int32_t ckpt_every, int32_t prec);
+
+/* w = (H0 + u Hc) v in the reduced basis (one gather per antiparallel bond).
+ * v, w: pe->dim amplitudes, not overlapping.  Errors: KG_EINVAL, KG_EDEVICE. */
+kg_status xxz_pe_apply(const kg_xxz* h, const kg_pe* pe, double u, int32_t prec, const void* v,
+                       void* w, void* stream);
+
+/* krylov_expv in the reduced basis.  Arguments, workspace rules and errors as
+ * krylov_expv (workspace from kg_pe_workspace_bytes). */
+kg_status krylov_expv_pe(const kg_xxz* h, const kg_pe* pe, double u, double t, const kg_krylov* k,
+                         int32_t prec, const void* v_in, void* v_out, void* ws, size_t ws_bytes,
+                         int32_t* m_eff_dev, void* stream);
+
+/* grape_forward in the reduced basis (states from kg_pe_states_bytes). */
+kg_status grape_forward_pe(const kg_xxz* h, const kg_pe* pe, const double* u_dev, int32_t N,
+                           double dt, const kg_krylov* k, int32_t prec, const void* psi0,
+                           const void* target, double* F_dev, double* beta_dev, void* states,
+                           int32_t ckpt_every, void* ws, size_t ws_bytes, void* stream);
+
+/* Gradients in the reduced basis.  variant selects the full-space entry point
+ * it mirrors; nodes is the quadrature's node count (1..KG_MAX_NODES) and must
+ * be 0 for the other variants.  The quadrature and first-order variants need
+ * the extended workspace (kg_pe_workspace_bytes with extended = 1). */
+#define KG_GRAD_ZEROTH 0       /* grape_gradient */
+#define KG_GRAD_CENTRED 1      /* grape_gradient_centred */
+#define KG_GRAD_FIRST_ORDER 2  /* grape_gradient_first_order */
+#define KG_GRAD_QUADRATURE 3   /* grape_gradient_quadrature */
+kg_status grape_gradient_pe(const kg_xxz* h, const kg_pe* pe, const double* u_dev, int32_t N,
+                            double dt, const kg_krylov* k, int32_t prec, const void* psi0,
+                            const void* target, double* F_dev, double* beta_dev, double* grad_dev,
+                            void* states, int32_t ckpt_every, int32_t states_valid,
+                            int32_t variant, int32_t nodes, void* ws, size_t ws_bytes,
+                            void* stream);
 
 /* ---------------------------------------------------------------- batched form
  * Many independent chains (different L, Delta, N, m) evaluated by one

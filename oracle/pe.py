@@ -118,6 +118,31 @@ def apply_h_pe(B: PEBasis, J: float, Delta: float, sz_sites: int, u: float,
     return y
 
 
+def apply_h_pe_rows(B: PEBasis, J: float, Delta: float, sz_sites: int, u: float,
+                    x: np.ndarray, rows) -> np.ndarray:
+    """Selected entries y_b of the reduced (H0 + u Hc) x, one row at a time
+    (for spot checks at sizes where the whole product is too slow here)."""
+    L = B.L
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for i, b in enumerate(rows):
+        r = int(B.reps[b])
+        val = complex(diag_pe_rows(B, J, Delta, sz_sites, u, r)) * x[b]
+        for p in range(L - 1):
+            if ((r >> p) ^ (r >> (p + 1))) & 1:
+                a = int(B.index(np.array([r ^ (3 << p)]))[0])
+                val += 0.5 * J * np.sqrt(B.n[b] / B.n[a]) * x[a]
+        out[i] = val
+    return out
+
+
+def diag_pe_rows(B: PEBasis, J: float, Delta: float, sz_sites: int, u: float, r: int) -> float:
+    s = np.array([r], dtype=np.int64)
+    d = float(model.diag_h0(B.L, J, Delta, s).real[0])
+    if sz_sites:
+        d += u * float(model.sz_control_diag(B.L, sz_sites, s).real[0])
+    return d
+
+
 def hc_pe(B: PEBasis, sz_sites: int) -> np.ndarray:
     """Diagonal of the reduced control operator."""
     return model.sz_control_diag(B.L, sz_sites, B.reps).real

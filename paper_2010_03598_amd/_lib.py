@@ -25,6 +25,12 @@ KG_HC_SZ = 1
 KG_MAX_M = 64
 KG_MIN_L = 2
 KG_MAX_L = 30
+KG_PE_MAX_L = 32
+
+KG_GRAD_ZEROTH = 0
+KG_GRAD_CENTRED = 1
+KG_GRAD_FIRST_ORDER = 2
+KG_GRAD_QUADRATURE = 3
 
 
 class KgXxz(ctypes.Structure):
@@ -46,6 +52,11 @@ class KgChain(ctypes.Structure):
                 ("off_ws", ctypes.c_int64)]
 
 
+class KgPe(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("K", ctypes.c_int32), ("dim", ctypes.c_int64),
+                ("tables", ctypes.c_void_p)]
+
+
 class KgError(RuntimeError):
     def __init__(self, fn: str, status: int, message: str):
         super().__init__(f"{fn} failed with status {status}: {message}")
@@ -59,6 +70,7 @@ _D = ctypes.c_double
 _SZ = ctypes.c_size_t
 _PX = ctypes.POINTER(KgXxz)
 _PK = ctypes.POINTER(KgKrylov)
+_PPE = ctypes.POINTER(KgPe)
 
 # name -> (restype, argtypes); mirrors include/kgrape.h
 SIGNATURES = {
@@ -85,6 +97,18 @@ SIGNATURES = {
     "grape_gradient_batched": (_I32, [_P, _P, _I32, _I32, _P, ctypes.c_int64, _P, _P, ctypes.c_int64,
                                       _P, ctypes.c_int64, _P, _P, _P, _P, _SZ, _P, _P]),
     "kg_profile_end": (_I32, [_P, _P, _P]),
+    "kg_pe_dim": (ctypes.c_int64, [_I32, _I32]),
+    "kg_pe_tables_bytes": (_SZ, [_I32, _I32]),
+    "kg_pe_tables_host": (_I32, [_I32, _I32, _P, _SZ]),
+    "kg_pe_build": (_I32, [_I32, _I32, _P, _SZ, _PPE]),
+    "kg_pe_workspace_bytes": (_SZ, [_PPE, _PK, _I32, _I32]),
+    "kg_pe_states_bytes": (_SZ, [_PPE, _I32, _I32, _I32]),
+    "xxz_pe_apply": (_I32, [_PX, _PPE, _D, _I32, _P, _P, _P]),
+    "krylov_expv_pe": (_I32, [_PX, _PPE, _D, _D, _PK, _I32, _P, _P, _P, _SZ, _P, _P]),
+    "grape_forward_pe": (_I32, [_PX, _PPE, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _I32, _P,
+                                _SZ, _P]),
+    "grape_gradient_pe": (_I32, [_PX, _PPE, _P, _I32, _D, _PK, _I32, _P, _P, _P, _P, _P, _P, _I32,
+                                 _I32, _I32, _I32, _P, _SZ, _P]),
 }
 
 PROF_CLASSES = ["pass_a", "pass_b", "combine", "bracket", "overlap", "hv"]

@@ -59,10 +59,10 @@ kg_status hip_fail(hipError_t e, const char* where) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-kg_status check_xxz(const kg_xxz* h) {
+kg_status check_xxz(const kg_xxz* h, int max_L = KG_MAX_L) {
   if (!h) return fail(KG_EINVAL, "h is NULL");
-  if (h->L < KG_MIN_L || h->L > KG_MAX_L)
-    return fail(KG_EINVAL, "L=%d outside [%d, %d]", h->L, KG_MIN_L, KG_MAX_L);
+  if (h->L < KG_MIN_L || h->L > max_L)
+    return fail(KG_EINVAL, "L=%d outside [%d, %d]", h->L, KG_MIN_L, max_L);
   if (!isfinite(h->J) || !isfinite(h->Delta)) return fail(KG_EINVAL, "J and Delta must be finite");
   if (h->hc_kind != KG_HC_SX && h->hc_kind != KG_HC_SZ)
     return fail(KG_EINVAL, "unknown hc_kind %d", h->hc_kind);
@@ -129,40 +129,59 @@ HvArgs make_hv(const kg_xxz* h, const double* u_ptr, double u_val) {
   return a;
 }
 
-size_t slot_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
-  return ws_fixed_bytes() + align_up(vec_bytes(h->L, prec) * (size_t)(k->m - 1), 256) +
-         align_up(vec_bytes(h->L, prec), 256);
+size_t vbytes(uint64_t D, int32_t prec) { return (size_t)D * (prec == KG_C128 ? 16 : 8); }
+
+size_t slot_bytes_d(uint64_t D, const kg_krylov* k, int32_t prec) {
+  return ws_fixed_bytes() + align_up(vbytes(D, prec) * (size_t)(k->m - 1), 256) +
+         align_up(vbytes(D, prec), 256);
+}
+
+// workspace of vectors of D amplitudes; `extended` adds the two node vectors
+size_t ws_bytes_d(uint64_t D, const kg_krylov* k, int32_t prec, bool extended) {
+  return 2 * slot_bytes_d(D, k, prec) + align_up(vbytes(D, prec), 256) +
+         (extended ? 2 * align_up(vbytes(D, prec), 256) : 0);
 }
 
 // The workspace holds two Krylov slots (scalars, reduction partials, m-1
 // basis vectors and the H v_k vector each) and one costate vector.  Slot 0 serves single calls and
 // the backward sweep, slot 1 the segment recomputation advanced beside it.
-kg_status carve(void* ws, size_t ws_bytes, const kg_xxz* h, const kg_krylov* k, int32_t prec,
-                Workspace* out0, Workspace* out1) {
+size_t states_bytes_d(uint64_t D, int32_t N, int32_t ckpt_every, int32_t prec) {
+  const size_t vb = vbytes(D, prec);
+  if (ckpt_every == 0) return vb * (size_t)N;
+  const int nseg = (N + ckpt_every - 1) / ckpt_every;
+  const int nbuf = nseg > 1 ? 2 : 1;
+  return vb * (size_t)(nseg - 1 + nbuf * ckpt_every);
+}
+
+kg_status carve_d(void* ws, size_t ws_bytes, uint64_t D, const kg_krylov* k, int32_t prec,
+                  Workspace* out0, Workspace* out1, bool extended = false) {
   if (!ws) return fail(KG_EWORKSPACE, "workspace is NULL");
   if ((uintptr_t)ws % 256) return fail(KG_EWORKSPACE, "workspace is not 256-byte aligned");
-  const size_t need = kg_workspace_bytes(h, k, prec);
+  const size_t need = ws_bytes_d(D, k, prec, extended);
   if (ws_bytes < need)
-    return fail(KG_EWORKSPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    return fail(KG_EWORKSPACE, "workspace has %zu bytes, needs %zu%s", ws_bytes, need,
+                extended ? " (extended)" : "");
   char* p = static_cast<char*>(ws);
+  const size_t vb = align_up(vbytes(D, prec), 256);
   Workspace* outs[2] = {out0, out1};
   for (int i = 0; i < 2; ++i) {
     Workspace* o = outs[i];
-    char* q = p + (size_t)i * slot_bytes(h, k, prec);
+    char* q = p + (size_t)i * slot_bytes_d(D, k, prec);
     if (!o) continue;
     o->st = reinterpret_cast<KState*>(q);
     q += align_up(sizeof(KState), 256);
     o->partials = reinterpret_cast<cplx_d*>(q);
     q += align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
     o->basis = q;
-    q += align_up(vec_bytes(h->L, prec) * (size_t)(k->m - 1), 256);
+    q += align_up(vbytes(D, prec) * (size_t)(k->m - 1), 256);
     o->hx = q;
-    o->lam = p + 2 * slot_bytes(h, k, prec);
-    o->node_a = nullptr;
-    o->node_b = nullptr;
+    o->lam = p + 2 * slot_bytes_d(D, k, prec);
+    o->node_a = extended ? static_cast<char*>(o->lam) + vb : nullptr;
+    o->node_b = extended ? static_cast<char*>(o->lam) + 2 * vb : nullptr;
   }
   return KG_OK;
 }
+
 
 // Where the forward states live in the caller's state buffer.  With
 // checkpoints every c slices, segment q holds slices (q c, (q+1) c]; psi_{(q+1)c}
@@ -218,6 +237,8 @@ struct SweepArgs {
   Workspace ws;    // slot 0: single calls and the backward sweep
   Workspace ws1;   // slot 1: recomputation beside the backward sweep
   hipStream_t stream;
+  const PeArgs* pe = nullptr;   // reduced basis (nullptr: full space)
+  size_t vb = 0;                // bytes of one vector
 };
 
 KrylovCall krylov_call(const SweepArgs& a, int j, double t, const void* in, void* out) {
@@ -232,6 +253,7 @@ KrylovCall krylov_call(const SweepArgs& a, int j, double t, const void* in, void
   c.v_in = in;
   c.v_out = out;
   c.m_eff_out = nullptr;
+  c.pe = a.pe;
   return c;
 }
 
@@ -244,7 +266,7 @@ kg_status forward_sweep(const SweepArgs& a, const States& S, double* F_dev, doub
   if (prof) profiler_start(prof, a.stream);
   KG_HIP(launch_overlap(a.prec, a.geo.D, a.target, S.at(a.N), a.ws, F_dev, beta_dev, a.stream),
          "overlap");
-  if (prof) profiler_stop(prof, a.stream, kProfOverlap, 2.0 * vec_bytes(a.h->L, a.prec));
+  if (prof) profiler_stop(prof, a.stream, kProfOverlap, 2.0 * a.vb);
   return KG_OK;
 }
 
@@ -267,6 +289,7 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
                          double* grad_dev, bool centred = false, const Quadrature* Q = nullptr,
                          bool first_order = false) {
   const HvArgs hc = make_hv(a.h, nullptr, 0.0);
+  const uint32_t* pe_reps = a.pe ? a.pe->reps : nullptr;
   const void* lam = a.target;
   for (int q = S.nseg - 1; q >= 0; --q) {
     const int cs = (S.c == 0) ? 0 : q * S.c;
@@ -284,27 +307,32 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
           const KrylovCall cb = krylov_call(a, j, -(a.dt - Q->s[q]), lam, a.ws.node_b);
           KG_HIP(launch_krylov_pair(ca, a.ws, cb, a.ws1, a.stream), "quadrature node states");
           KG_HIP(launch_bracket(a.prec, hc, a.geo.D, a.ws.node_b, a.ws.node_a, Q->w[q], beta_dev,
-                                a.ws, grad_dev + (j - 1), a.stream, q > 0),
+                                a.ws, grad_dev + (j - 1), a.stream, q > 0, 0.0, pe_reps),
                  "quadrature bracket");
         }
       } else {
         Profiler* prof = profiler_for_launch();
         if (prof) profiler_start(prof, a.stream);
         KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.at(j), a.dt, beta_dev, a.ws,
-                              grad_dev + (j - 1), a.stream),
+                              grad_dev + (j - 1), a.stream, false, 0.0, pe_reps),
                "gradient bracket");
-        if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * vec_bytes(a.h->L, a.prec));
+        if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * a.vb);
         if (first_order) {
           const HvArgs hj = make_hv(a.h, a.u_dev + (j - 1), 0.0);
           const double c1 = 0.5 * a.dt * a.dt;
-          KG_HIP(launch_hv(a.prec, hj, a.geo, S.at(j), a.ws.node_a, a.stream), "H psi_j");
-          KG_HIP(launch_hv(a.prec, hj, a.geo, lam, a.ws.node_b, a.stream), "H lambda_j");
+          if (a.pe) {
+            KG_HIP(launch_hv_pe(a.prec, hj, *a.pe, S.at(j), a.ws.node_a, a.stream), "H psi_j");
+            KG_HIP(launch_hv_pe(a.prec, hj, *a.pe, lam, a.ws.node_b, a.stream), "H lambda_j");
+          } else {
+            KG_HIP(launch_hv(a.prec, hj, a.geo, S.at(j), a.ws.node_a, a.stream), "H psi_j");
+            KG_HIP(launch_hv(a.prec, hj, a.geo, lam, a.ws.node_b, a.stream), "H lambda_j");
+          }
           // - (i dt^2/2) <H lambda|Hc psi> + (i dt^2/2) <lambda|Hc H psi>
           KG_HIP(launch_bracket(a.prec, hc, a.geo.D, a.ws.node_b, S.at(j), 0.0, beta_dev, a.ws,
-                                grad_dev + (j - 1), a.stream, true, -c1),
+                                grad_dev + (j - 1), a.stream, true, -c1, pe_reps),
                  "first-order bracket");
           KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, a.ws.node_a, 0.0, beta_dev, a.ws,
-                                grad_dev + (j - 1), a.stream, true, c1),
+                                grad_dev + (j - 1), a.stream, true, c1, pe_reps),
                  "first-order bracket");
         }
       }
@@ -331,7 +359,7 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
   }
   if (centred) {
     KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, a.psi0, a.dt, beta_dev, a.ws, &a.ws.st->g0,
-                          a.stream),
+                          a.stream, false, 0.0, pe_reps),
            "gradient bracket at t = 0");
     KG_HIP(launch_centre(grad_dev, a.N, &a.ws.st->g0, a.stream), "centred gradient");
   }
@@ -340,8 +368,8 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
 
 kg_status check_sweep(const kg_xxz* h, const double* u_dev, int32_t N, double dt, const kg_krylov* k,
                       int32_t prec, const void* psi0, const void* target, void* states,
-                      int32_t ckpt_every) {
-  KG_CHECK(check_xxz(h));
+                      int32_t ckpt_every, int max_L = KG_MAX_L) {
+  KG_CHECK(check_xxz(h, max_L));
   KG_CHECK(check_krylov(k));
   KG_CHECK(check_prec(prec));
   if (!u_dev) return fail(KG_EINVAL, "u_dev is NULL");
@@ -461,7 +489,7 @@ int32_t kg_version(void) { return 1; }
 
 size_t kg_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
   if (check_xxz(h) != KG_OK || check_krylov(k) != KG_OK || check_prec(prec) != KG_OK) return 0;
-  return 2 * slot_bytes(h, k, prec) + align_up(vec_bytes(h->L, prec), 256);
+  return ws_bytes_d((uint64_t)1 << h->L, k, prec, false);
 }
 
 size_t kg_states_bytes(const kg_xxz* h, int32_t N, int32_t ckpt_every, int32_t prec) {
@@ -470,11 +498,7 @@ size_t kg_states_bytes(const kg_xxz* h, int32_t N, int32_t ckpt_every, int32_t p
     fail(KG_EINVAL, "bad N=%d or ckpt_every=%d", N, ckpt_every);
     return 0;
   }
-  const size_t vb = vec_bytes(h->L, prec);
-  if (ckpt_every == 0) return vb * (size_t)N;
-  const int nseg = (N + ckpt_every - 1) / ckpt_every;
-  const int nbuf = nseg > 1 ? 2 : 1;
-  return vb * (size_t)(nseg - 1 + nbuf * ckpt_every);
+  return states_bytes_d((uint64_t)1 << h->L, N, ckpt_every, prec);
 }
 
 kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void* w, void* stream) {
@@ -493,24 +517,32 @@ kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void
   return ok();
 }
 
-kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, int32_t prec,
-                      const void* v_in, void* v_out, void* ws, size_t ws_bytes, int32_t* m_eff_dev,
-                      void* stream) {
-  KG_CHECK(check_xxz(h));
+namespace {
+
+// The vector space of a sweep: the full 2^L space, or the reduced basis.
+struct Space {
+  Geo geo;
+  const PeArgs* pe;   // nullptr: full space
+};
+
+kg_status expv_impl(const kg_xxz* h, const Space& sp, double u, double t, const kg_krylov* k,
+                    int32_t prec, const void* v_in, void* v_out, void* ws, size_t ws_bytes,
+                    int32_t* m_eff_dev, void* stream) {
   KG_CHECK(check_krylov(k));
   KG_CHECK(check_prec(prec));
   if (!isfinite(u) || !isfinite(t)) return fail(KG_EINVAL, "u and t must be finite");
   KG_CHECK(check_vec(v_in, prec, "v_in"));
   KG_CHECK(check_vec(v_out, prec, "v_out"));
-  if (v_in != v_out && overlap(v_in, v_out, vec_bytes(h->L, prec)))
+  if (v_in != v_out && overlap(v_in, v_out, vbytes(sp.geo.D, prec)))
     return fail(KG_EINVAL, "v_in and v_out overlap without being equal");
   if (m_eff_dev && (uintptr_t)m_eff_dev % 4) return fail(KG_EINVAL, "m_eff_dev misaligned");
   Workspace W;
-  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, nullptr));
+  KG_CHECK(carve_d(ws, ws_bytes, sp.geo.D, k, prec, &W, nullptr));
   const hipStream_t s = (hipStream_t)stream;
   KrylovCall c;
   c.hv = make_hv(h, nullptr, u);
-  c.geo = make_geo(h->L, prec, tile_override_from_env());
+  c.geo = sp.geo;
+  c.pe = sp.pe;
   c.prec = prec;
   c.m = k->m;
   c.reorth = k->reorth;
@@ -524,24 +556,41 @@ kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, i
   return ok();
 }
 
-kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
-                        const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
-                        double* F_dev, double* beta_dev, void* states, int32_t ckpt_every, void* ws,
-                        size_t ws_bytes, void* stream) {
-  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
+kg_status forward_impl(const kg_xxz* h, const Space& sp, const double* u_dev, int32_t N, double dt,
+                       const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                       double* F_dev, double* beta_dev, void* states, int32_t ckpt_every, void* ws,
+                       size_t ws_bytes, void* stream, const char* name) {
   if (!F_dev || !beta_dev) return fail(KG_EINVAL, "F_dev and beta_dev are required");
   Workspace W, W1;
-  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, &W1));
-  SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
-              make_geo(h->L, prec, tile_override_from_env()), W, W1, (hipStream_t)stream};
-  const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
-  KG_HIP(launch_init(W.st, a.stream), "grape_forward init");
-  KG_HIP(launch_init(W1.st, a.stream), "grape_forward init");
+  KG_CHECK(carve_d(ws, ws_bytes, sp.geo.D, k, prec, &W, &W1));
+  SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target, sp.geo, W, W1, (hipStream_t)stream,
+              sp.pe, vbytes(sp.geo.D, prec)};
+  const States S = make_states(N, ckpt_every, states, a.vb, psi0);
+  KG_HIP(launch_init(W.st, a.stream), name);
+  KG_HIP(launch_init(W1.st, a.stream), name);
   KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
   return ok();
 }
 
-namespace {
+kg_status gradient_core(const kg_xxz* h, const Space& sp, const double* u_dev, int32_t N,
+                        double dt, const kg_krylov* k, int32_t prec, const void* psi0,
+                        const void* target, double* F_dev, double* beta_dev, double* grad_dev,
+                        void* states, int32_t ckpt_every, int32_t states_valid, void* ws,
+                        size_t ws_bytes, void* stream, bool centred, const char* name,
+                        const Quadrature* Q, bool first_order) {
+  if (!beta_dev || !grad_dev) return fail(KG_EINVAL, "beta_dev and grad_dev are required");
+  if (states_valid != 0 && states_valid != 1) return fail(KG_EINVAL, "states_valid must be 0 or 1");
+  Workspace W, W1;
+  KG_CHECK(carve_d(ws, ws_bytes, sp.geo.D, k, prec, &W, &W1, Q != nullptr || first_order));
+  SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target, sp.geo, W, W1, (hipStream_t)stream,
+              sp.pe, vbytes(sp.geo.D, prec)};
+  const States S = make_states(N, ckpt_every, states, a.vb, psi0);
+  KG_HIP(launch_init(W.st, a.stream), name);
+  KG_HIP(launch_init(W1.st, a.stream), name);
+  if (!states_valid) KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
+  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev, centred, Q, first_order));
+  return ok();
+}
 
 kg_status gradient_impl(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
                         const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
@@ -550,26 +599,10 @@ kg_status gradient_impl(const kg_xxz* h, const double* u_dev, int32_t N, double 
                         void* stream, bool centred, const char* name,
                         const Quadrature* Q = nullptr, bool first_order = false) {
   KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
-  if (!beta_dev || !grad_dev) return fail(KG_EINVAL, "beta_dev and grad_dev are required");
-  if (states_valid != 0 && states_valid != 1) return fail(KG_EINVAL, "states_valid must be 0 or 1");
-  Workspace W, W1;
-  KG_CHECK(carve(ws, ws_bytes, h, k, prec, &W, &W1));
-  if (Q || first_order) {
-    const size_t base = kg_workspace_bytes(h, k, prec);
-    const size_t need = kg_extended_workspace_bytes(h, k, prec);
-    if (ws_bytes < need)
-      return fail(KG_EWORKSPACE, "workspace has %zu bytes, %s needs %zu", ws_bytes, name, need);
-    W.node_a = static_cast<char*>(ws) + base;
-    W.node_b = static_cast<char*>(W.node_a) + align_up(vec_bytes(h->L, prec), 256);
-  }
-  SweepArgs a{h, u_dev, N, dt, k, prec, psi0, target,
-              make_geo(h->L, prec, tile_override_from_env()), W, W1, (hipStream_t)stream};
-  const States S = make_states(N, ckpt_every, states, vec_bytes(h->L, prec), psi0);
-  KG_HIP(launch_init(W.st, a.stream), name);
-  KG_HIP(launch_init(W1.st, a.stream), name);
-  if (!states_valid) KG_CHECK(forward_sweep(a, S, F_dev, beta_dev));
-  KG_CHECK(backward_sweep(a, S, beta_dev, grad_dev, centred, Q, first_order));
-  return ok();
+  const Space sp{make_geo(h->L, prec, tile_override_from_env()), nullptr};
+  return gradient_core(h, sp, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev,
+                       states, ckpt_every, states_valid, ws, ws_bytes, stream, centred, name, Q,
+                       first_order);
 }
 
 // Gauss-Legendre nodes and weights on [-1, 1]: Newton's iteration on P_n
@@ -597,7 +630,39 @@ void gauss_legendre(int n, double* x, double* w) {
   }
 }
 
+// Nodes and weights of the n-point rule on [0, dt].
+kg_status make_quadrature(int32_t nodes, double dt, Quadrature* Q) {
+  if (nodes < 1 || nodes > KG_MAX_NODES)
+    return fail(KG_EINVAL, "nodes=%d outside [1, %d]", nodes, KG_MAX_NODES);
+  Q->n = nodes;
+  double x[KG_MAX_NODES], w[KG_MAX_NODES];
+  gauss_legendre(nodes, x, w);
+  for (int q = 0; q < nodes; ++q) {
+    Q->s[q] = 0.5 * dt * (x[q] + 1.0);
+    Q->w[q] = 0.5 * dt * w[q];
+  }
+  return KG_OK;
+}
+
 }  // namespace
+
+kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, int32_t prec,
+                      const void* v_in, void* v_out, void* ws, size_t ws_bytes, int32_t* m_eff_dev,
+                      void* stream) {
+  KG_CHECK(check_xxz(h));
+  const Space sp{make_geo(h->L, prec, tile_override_from_env()), nullptr};
+  return expv_impl(h, sp, u, t, k, prec, v_in, v_out, ws, ws_bytes, m_eff_dev, stream);
+}
+
+kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                        const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
+                        double* F_dev, double* beta_dev, void* states, int32_t ckpt_every, void* ws,
+                        size_t ws_bytes, void* stream) {
+  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every));
+  const Space sp{make_geo(h->L, prec, tile_override_from_env()), nullptr};
+  return forward_impl(h, sp, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, states,
+                      ckpt_every, ws, ws_bytes, stream, "grape_forward");
+}
 
 kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
                          const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
@@ -609,9 +674,8 @@ kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double
 }
 
 size_t kg_extended_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec) {
-  const size_t base = kg_workspace_bytes(h, k, prec);
-  if (!base) return 0;
-  return base + 2 * align_up(vec_bytes(h->L, prec), 256);
+  if (check_xxz(h) != KG_OK || check_krylov(k) != KG_OK || check_prec(prec) != KG_OK) return 0;
+  return ws_bytes_d((uint64_t)1 << h->L, k, prec, true);
 }
 
 kg_status grape_gradient_quadrature(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
@@ -620,16 +684,8 @@ kg_status grape_gradient_quadrature(const kg_xxz* h, const double* u_dev, int32_
                                     double* grad_dev, void* states, int32_t ckpt_every,
                                     int32_t states_valid, int32_t nodes, void* ws,
                                     size_t ws_bytes, void* stream) {
-  if (nodes < 1 || nodes > KG_MAX_NODES)
-    return fail(KG_EINVAL, "nodes=%d outside [1, %d]", nodes, KG_MAX_NODES);
   Quadrature Q;
-  Q.n = nodes;
-  double x[KG_MAX_NODES], w[KG_MAX_NODES];
-  gauss_legendre(nodes, x, w);
-  for (int q = 0; q < nodes; ++q) {
-    Q.s[q] = 0.5 * dt * (x[q] + 1.0);
-    Q.w[q] = 0.5 * dt * w[q];
-  }
+  KG_CHECK(make_quadrature(nodes, dt, &Q));
   return gradient_impl(h, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev, states,
                        ckpt_every, states_valid, ws, ws_bytes, stream, false,
                        "grape_gradient_quadrature", &Q);
@@ -776,6 +832,294 @@ kg_status kg_profile_end(int64_t* launches, double* ms, double* bytes) {
   for (auto& e : p->ev) hipEventDestroy(e);
   delete p;
   return st == KG_OK ? ok() : st;
+}
+
+// ---------------------------------------------------------------------- reduced basis
+
+namespace {
+
+// Pascal's triangle up to n = 32 (exact in 64 bits).
+struct Pascal {
+  uint64_t c[kPeBinom][kPeBinom];
+  Pascal() {
+    memset(c, 0, sizeof(c));
+    for (int n = 0; n < kPeBinom; ++n) {
+      c[n][0] = 1;
+      for (int k = 1; k <= n; ++k) c[n][k] = c[n - 1][k - 1] + (k < n ? c[n - 1][k] : 0);
+    }
+  }
+};
+
+const Pascal& pascal() {
+  static const Pascal p;
+  return p;
+}
+
+uint32_t reverse_bits(uint32_t s, int L) {
+  uint32_t r = 0;
+  for (int b = 0; b < L; ++b) r |= ((s >> b) & 1u) << (L - 1 - b);
+  return r;
+}
+
+// Number of orbits {s, Pi s} among the L-bit patterns with K zero bits: the
+// sector size plus its palindromes, halved.  A palindrome is fixed by its first
+// floor(L/2) bits and (L odd) its middle bit, so it has an even number of zero
+// bits outside the middle.
+int64_t pe_dim(int L, int K) {
+  const Pascal& P = pascal();
+  const uint64_t sector = P.c[L][K];
+  uint64_t pal = 0;
+  if (L % 2 == 1 || K % 2 == 0) pal = P.c[L / 2][K / 2];
+  return (int64_t)((sector + pal) / 2);
+}
+
+// Table layout in the caller's buffer: binomials (uint32, kPeBinom^2), orbit
+// representatives (uint32, dim), index by combinatorial rank (int32, C(L,K)),
+// each at a 256-byte boundary.
+struct PeLayout {
+  size_t off_reps, off_index, total;
+};
+
+PeLayout pe_layout(int L, int K) {
+  PeLayout o;
+  o.off_reps = align_up(sizeof(uint32_t) * kPeBinom * kPeBinom, 256);
+  o.off_index = o.off_reps + align_up(sizeof(uint32_t) * (size_t)pe_dim(L, K), 256);
+  o.total = o.off_index + align_up(sizeof(int32_t) * (size_t)pascal().c[L][K], 256);
+  return o;
+}
+
+kg_status check_pe_shape(int32_t L, int32_t K) {
+  if (L < KG_MIN_L || L > KG_PE_MAX_L)
+    return fail(KG_EINVAL, "L=%d outside [%d, %d]", L, KG_MIN_L, KG_PE_MAX_L);
+  if (K < 0 || K > L) return fail(KG_EINVAL, "K=%d outside [0, L=%d]", K, L);
+  return KG_OK;
+}
+
+kg_status check_pe(const kg_pe* pe) {
+  if (!pe) return fail(KG_EINVAL, "pe is NULL");
+  KG_CHECK(check_pe_shape(pe->L, pe->K));
+  if (pe->dim != pe_dim(pe->L, pe->K))
+    return fail(KG_EINVAL, "pe->dim=%lld is not the dimension %lld of L=%d, K=%d",
+                (long long)pe->dim, (long long)pe_dim(pe->L, pe->K), pe->L, pe->K);
+  if (!pe->tables || (uintptr_t)pe->tables % 256)
+    return fail(KG_EINVAL, "pe->tables missing or not 256-byte aligned");
+  return KG_OK;
+}
+
+// The chain must conserve the excitation number and the mirror parity: an
+// S^z control on a mirror-symmetric set of sites.
+kg_status check_pe_chain(const kg_xxz* h, const kg_pe* pe) {
+  KG_CHECK(check_xxz(h, KG_PE_MAX_L));
+  KG_CHECK(check_pe(pe));
+  if (h->L != pe->L) return fail(KG_EINVAL, "h->L=%d differs from pe->L=%d", h->L, pe->L);
+  if (h->hc_kind != KG_HC_SZ)
+    return fail(KG_EINVAL, "the reduced basis needs an S^z control (KG_HC_SZ)");
+  for (int i = 1; i <= h->L; ++i)
+    if (((h->hc_sites >> (i - 1)) & 1ull) != ((h->hc_sites >> (h->L - i)) & 1ull))
+      return fail(KG_EINVAL, "hc_sites is not mirror-symmetric (site %d vs %d)", i, h->L + 1 - i);
+  return KG_OK;
+}
+
+PeArgs pe_args(const kg_pe* pe) {
+  const PeLayout o = pe_layout(pe->L, pe->K);
+  const char* t = static_cast<const char*>(pe->tables);
+  PeArgs a;
+  memset(&a, 0, sizeof(a));
+  a.binom = reinterpret_cast<const uint32_t*>(t);
+  a.reps = reinterpret_cast<const uint32_t*>(t + o.off_reps);
+  a.index = reinterpret_cast<const int32_t*>(t + o.off_index);
+  a.L = pe->L;
+  a.K = pe->K;
+  a.dim = (uint32_t)pe->dim;
+  a.nsec = (uint32_t)pascal().c[pe->L][pe->K];
+  return a;
+}
+
+// Lanczos tiles of the reduced basis: four amplitudes per thread, tiles of
+// 2^TB (TB = 8..12) amplitudes, the smallest TB that keeps the tile count at
+// or below 512; beyond kMaxGrid tiles the count is padded to a multiple of
+// the grid (the padded tail is masked like the ragged last tile).
+Geo make_geo_pe(int L, uint64_t dim) {
+  Geo g;
+  memset(&g, 0, sizeof(g));
+  g.L = L;
+  g.D = (uint32_t)dim;
+  int tb = 8;
+  while (tb < 12 && ((dim + ((uint64_t)1 << tb) - 1) >> tb) > 512) ++tb;
+  uint64_t nt = (dim + ((uint64_t)1 << tb) - 1) >> tb;
+  if (nt < 1) nt = 1;
+  if (nt > (uint64_t)kMaxGrid) nt = (nt + kMaxGrid - 1) / kMaxGrid * kMaxGrid;
+  g.TB = tb;
+  g.RB = 2;
+  g.WB = tb - 8;
+  g.small = 1;
+  g.ntiles = (uint32_t)nt;
+  g.grid = (int)(nt < (uint64_t)kMaxGrid ? nt : (uint64_t)kMaxGrid);
+  return g;
+}
+
+}  // namespace
+
+int64_t kg_pe_dim(int32_t L, int32_t K) {
+  if (check_pe_shape(L, K) != KG_OK) return 0;
+  return pe_dim(L, K);
+}
+
+size_t kg_pe_tables_bytes(int32_t L, int32_t K) {
+  if (check_pe_shape(L, K) != KG_OK) return 0;
+  return pe_layout(L, K).total;
+}
+
+kg_status kg_pe_tables_host(int32_t L, int32_t K, void* tables_host, size_t tables_bytes) {
+  KG_CHECK(check_pe_shape(L, K));
+  const PeLayout o = pe_layout(L, K);
+  if (!tables_host) return fail(KG_EINVAL, "tables_host is NULL");
+  if (tables_bytes < o.total)
+    return fail(KG_EWORKSPACE, "tables have %zu bytes, need %zu", tables_bytes, o.total);
+  const Pascal& P = pascal();
+  const uint64_t sector = P.c[L][K];
+  const int64_t dim = pe_dim(L, K);
+  char* host = static_cast<char*>(tables_host);
+  memset(host, 0, o.total);
+  uint32_t* binom = reinterpret_cast<uint32_t*>(host);
+  for (int n = 0; n < kPeBinom; ++n)
+    for (int k = 0; k < kPeBinom; ++k) binom[n * kPeBinom + k] = (uint32_t)P.c[n][k];
+  uint32_t* reps = reinterpret_cast<uint32_t*>(host + o.off_reps);
+  int32_t* index = reinterpret_cast<int32_t*>(host + o.off_index);
+  const uint64_t full = (L == 32) ? 0xFFFFFFFFull : ((1ull << L) - 1ull);
+  auto rank = [&](uint32_t s) {
+    uint64_t z = ~(uint64_t)s & full, r = 0;
+    for (int i = 1; z; ++i, z &= z - 1) r += P.c[__builtin_ctzll(z)][i];
+    return r;
+  };
+  // the sector's patterns (L-K one bits) in ascending order; an orbit's
+  // smaller member comes first and takes the next index
+  const int ones = L - K;
+  uint64_t v = ones ? ((1ull << ones) - 1ull) : 0ull;
+  int64_t next = 0;
+  uint64_t seen = 0;
+  while (true) {
+    const uint32_t s = (uint32_t)v;
+    const uint32_t rs = reverse_bits(s, L);
+    const uint64_t rk = rank(s);
+    if (s <= rs) {
+      reps[next] = s;
+      index[rk] = (int32_t)next;
+      ++next;
+    } else {
+      index[rk] = index[rank(rs)];
+    }
+    ++seen;
+    if (ones == 0) break;
+    // next pattern with the same number of one bits (Gosper)
+    const uint64_t c = v & (~v + 1ull);
+    const uint64_t r = v + c;
+    v = (((r ^ v) >> 2) / c) | r;
+    if (v > full) break;
+  }
+  if (seen != sector || next != dim)
+    return fail(KG_EINVAL, "internal: enumerated %llu states and %lld orbits, expected %llu, %lld",
+                (unsigned long long)seen, (long long)next, (unsigned long long)sector,
+                (long long)dim);
+  return ok();
+}
+
+kg_status kg_pe_build(int32_t L, int32_t K, void* tables_dev, size_t tables_bytes, kg_pe* pe) {
+  KG_CHECK(check_pe_shape(L, K));
+  if (!pe) return fail(KG_EINVAL, "pe is NULL");
+  if (!tables_dev || (uintptr_t)tables_dev % 256)
+    return fail(KG_EINVAL, "tables_dev missing or not 256-byte aligned");
+  const PeLayout o = pe_layout(L, K);
+  if (tables_bytes < o.total)
+    return fail(KG_EWORKSPACE, "tables have %zu bytes, need %zu", tables_bytes, o.total);
+  std::vector<char> host(o.total);
+  KG_CHECK(kg_pe_tables_host(L, K, host.data(), host.size()));
+  KG_HIP(hipMemcpy(tables_dev, host.data(), o.total, hipMemcpyHostToDevice), "kg_pe_build");
+  const int64_t dim = pe_dim(L, K);
+  pe->L = L;
+  pe->K = K;
+  pe->dim = dim;
+  pe->tables = tables_dev;
+  return ok();
+}
+
+size_t kg_pe_workspace_bytes(const kg_pe* pe, const kg_krylov* k, int32_t prec, int32_t extended) {
+  if (check_pe(pe) != KG_OK || check_krylov(k) != KG_OK || check_prec(prec) != KG_OK) return 0;
+  return ws_bytes_d((uint64_t)pe->dim, k, prec, extended != 0);
+}
+
+size_t kg_pe_states_bytes(const kg_pe* pe, int32_t N, int32_t ckpt_every, int32_t prec) {
+  if (check_pe(pe) != KG_OK || check_prec(prec) != KG_OK) return 0;
+  if (N < 1 || ckpt_every < 0 || ckpt_every > N) {
+    fail(KG_EINVAL, "bad N=%d or ckpt_every=%d", N, ckpt_every);
+    return 0;
+  }
+  return states_bytes_d((uint64_t)pe->dim, N, ckpt_every, prec);
+}
+
+kg_status xxz_pe_apply(const kg_xxz* h, const kg_pe* pe, double u, int32_t prec, const void* v,
+                       void* w, void* stream) {
+  KG_CHECK(check_pe_chain(h, pe));
+  KG_CHECK(check_prec(prec));
+  if (!isfinite(u)) return fail(KG_EINVAL, "u must be finite");
+  KG_CHECK(check_vec(v, prec, "v"));
+  KG_CHECK(check_vec(w, prec, "w"));
+  if (overlap(v, w, vbytes((uint64_t)pe->dim, prec))) return fail(KG_EINVAL, "v and w overlap");
+  const PeArgs pa = pe_args(pe);
+  KG_HIP(launch_hv_pe(prec, make_hv(h, nullptr, u), pa, v, w, (hipStream_t)stream), "xxz_pe_apply");
+  return ok();
+}
+
+kg_status krylov_expv_pe(const kg_xxz* h, const kg_pe* pe, double u, double t, const kg_krylov* k,
+                         int32_t prec, const void* v_in, void* v_out, void* ws, size_t ws_bytes,
+                         int32_t* m_eff_dev, void* stream) {
+  KG_CHECK(check_pe_chain(h, pe));
+  const PeArgs pa = pe_args(pe);
+  const Space sp{make_geo_pe(h->L, (uint64_t)pe->dim), &pa};
+  return expv_impl(h, sp, u, t, k, prec, v_in, v_out, ws, ws_bytes, m_eff_dev, stream);
+}
+
+kg_status grape_forward_pe(const kg_xxz* h, const kg_pe* pe, const double* u_dev, int32_t N,
+                           double dt, const kg_krylov* k, int32_t prec, const void* psi0,
+                           const void* target, double* F_dev, double* beta_dev, void* states,
+                           int32_t ckpt_every, void* ws, size_t ws_bytes, void* stream) {
+  KG_CHECK(check_pe_chain(h, pe));
+  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every, KG_PE_MAX_L));
+  const PeArgs pa = pe_args(pe);
+  const Space sp{make_geo_pe(h->L, (uint64_t)pe->dim), &pa};
+  return forward_impl(h, sp, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, states,
+                      ckpt_every, ws, ws_bytes, stream, "grape_forward_pe");
+}
+
+kg_status grape_gradient_pe(const kg_xxz* h, const kg_pe* pe, const double* u_dev, int32_t N,
+                            double dt, const kg_krylov* k, int32_t prec, const void* psi0,
+                            const void* target, double* F_dev, double* beta_dev, double* grad_dev,
+                            void* states, int32_t ckpt_every, int32_t states_valid,
+                            int32_t variant, int32_t nodes, void* ws, size_t ws_bytes,
+                            void* stream) {
+  KG_CHECK(check_pe_chain(h, pe));
+  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0, target, states, ckpt_every, KG_PE_MAX_L));
+  Quadrature Q;
+  const Quadrature* qp = nullptr;
+  switch (variant) {
+    case KG_GRAD_ZEROTH:
+    case KG_GRAD_CENTRED:
+    case KG_GRAD_FIRST_ORDER:
+      if (nodes != 0) return fail(KG_EINVAL, "nodes must be 0 for variant %d", variant);
+      break;
+    case KG_GRAD_QUADRATURE:
+      KG_CHECK(make_quadrature(nodes, dt, &Q));
+      qp = &Q;
+      break;
+    default:
+      return fail(KG_EINVAL, "unknown gradient variant %d", variant);
+  }
+  const PeArgs pa = pe_args(pe);
+  const Space sp{make_geo_pe(h->L, (uint64_t)pe->dim), &pa};
+  return gradient_core(h, sp, u_dev, N, dt, k, prec, psi0, target, F_dev, beta_dev, grad_dev,
+                       states, ckpt_every, states_valid, ws, ws_bytes, stream,
+                       variant == KG_GRAD_CENTRED, "grape_gradient_pe", qp,
+                       variant == KG_GRAD_FIRST_ORDER);
 }
 
 kg_status kg_debug_index_map(int32_t L, uint32_t s0, uint32_t count, int32_t* n_anti_dev,

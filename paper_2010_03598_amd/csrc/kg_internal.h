@@ -89,9 +89,21 @@ void profiler_stop(Profiler* p, hipStream_t s, int cls, double bytes);
 // ---- launchers (kg_kernels.hip); all enqueue on `s` and return hipSuccess or the launch error
 hipError_t launch_hv(int prec, const HvArgs& a, const Geo& g, const void* v, void* w, hipStream_t s);
 
+// The fixed-excitation, parity-even basis (device tables built by kg_pe_build).
+struct PeArgs {
+  const uint32_t* reps;    // orbit representatives (bit patterns), ascending
+  const int32_t* index;    // basis index of a sector state's orbit, by combinatorial rank
+  const uint32_t* binom;   // C(n, k) at [n * kPeBinom + k], n, k <= 32
+  int32_t L, K;
+  uint32_t dim;
+  uint32_t nsec;           // C(L, K): entries of `index`
+};
+constexpr int kPeBinom = 33;
+
 struct KrylovCall {
   HvArgs hv;
   Geo geo;
+  const PeArgs* pe = nullptr;  // reduced basis (nullptr: full 2^L space)
   int prec;
   int m;
   int reorth;
@@ -110,7 +122,10 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
                           double* F_dev, double* beta_dev, hipStream_t s);
 hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
                           double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
-                          hipStream_t s, bool accumulate = false, double coef_im = 0.0);
+                          hipStream_t s, bool accumulate = false, double coef_im = 0.0,
+                          const uint32_t* pe_reps = nullptr);
+hipError_t launch_hv_pe(int prec, const HvArgs& a, const PeArgs& p, const void* v, void* w,
+                        hipStream_t s);
 hipError_t launch_init(KState* st, hipStream_t s);
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
 hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s);

@@ -85,6 +85,74 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_hv(HvArgs a, Geo g, co
   }
 }
 
+// ---------------------------------------------------------------------- H v, reduced basis
+
+// y = (H0 + u Hc) x in the fixed-excitation, parity-even basis (Sec. III.A),
+// one output amplitude per thread.  With r the orbit label of output b and
+// n = 1 or 2 the orbit sizes,
+//   y_b = d(r) x_b + (J/2) sum_{antiparallel bonds p of r} sqrt(n_b / n_a) x_a,
+// a the orbit of r with bits p, p+1 exchanged.  a is found through the
+// combinatorial rank of the sector state over its zero bits (up spins):
+// rank(s) = sum_i C(z_i, i) for zero positions z_1 < z_2 < ...; exchanging a
+// zero at p with a one at p+1 (or back) changes the rank by C(p, j) with j the
+// zeros below p.  The S^z control is diagonal; the amplitudes x_a are gathered.
+template <typename R>
+__global__ void __launch_bounds__(256) k_hv_pe(HvArgs a, PeArgs p,
+                                               const typename VT<R>::T* __restrict__ x,
+                                               typename VT<R>::T* __restrict__ y) {
+  using V = typename VT<R>::T;
+  const int L = p.L;
+  const uint32_t full = (L == 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+  const uint32_t bondmask = (L >= 2) ? ((1u << (L - 1)) - 1u) : 0u;
+  const double u = control_value(a);
+  const R hJ = (R)a.half_J, czz = (R)a.c_zz, uR = (R)u;
+  const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
+  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < p.dim;
+       b += gridDim.x * blockDim.x) {
+    const uint32_t r = p.reps[b];
+    const bool nb2 = (__brev(r) >> (32 - L)) != r;
+    const int n_anti = (int)__popc((r ^ (r >> 1)) & bondmask);   // __popc is unsigned
+    R d = czz * (R)(L - 1 - 2 * n_anti);
+    if (a.hc_kind == 1) d += uR * ((R)(0.5 * a.sz_count) - (R)__popc(r & a.sz_mask));
+    const V xb = x[b];
+    R yr = d * xb.x, yi = d * xb.y;
+    uint32_t rank = 0;
+    {
+      uint32_t z = ~r & full;
+      int i = 1;
+      while (z) {
+        rank += p.binom[__builtin_ctz(z) * kPeBinom + i];
+        ++i;
+        z &= z - 1u;
+      }
+    }
+    uint32_t act = (r ^ (r >> 1)) & bondmask;
+    while (act) {
+      const int q = __builtin_ctz(act);
+      act &= act - 1u;
+      const uint32_t s2 = r ^ (3u << q);
+      const int below = __popc(~r & full & ((1u << q) - 1u));
+      const uint32_t dl = p.binom[q * kPeBinom + below];
+      const uint32_t rk = (((r >> q) & 1u) == 0u) ? rank + dl : rank - dl;
+      const bool na2 = (__brev(s2) >> (32 - L)) != s2;
+      const R w = (nb2 == na2) ? (R)1 : (nb2 ? rt2 : irt2);
+      // tables live in caller memory: an entry out of range gives NaN, never a stray load
+      const int32_t ai = (rk < p.nsec) ? p.index[rk] : -1;
+      if ((uint32_t)ai < p.dim) {
+        const V xa = x[ai];
+        yr += hJ * w * xa.x;
+        yi += hJ * w * xa.y;
+      } else {
+        yr = yi = (R)NAN;
+      }
+    }
+    V o;
+    o.x = yr;
+    o.y = yi;
+    y[b] = o;
+  }
+}
+
 // ---------------------------------------------------------------------- Lanczos passes
 
 struct LzArgs {
@@ -150,7 +218,9 @@ __device__ void finish_basis(const LzArgs& a, int m_eff, double fresh_alpha, dou
   }
 }
 
-template <typename R, int RB>
+// kYIn: y = H v_k was written to a.hx by a separate H v kernel (the reduced
+// basis); the pass then streams x and y instead of forming y on the tile.
+template <typename R, int RB, bool kYIn = false>
 __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
@@ -173,9 +243,26 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   for (uint32_t it = 0; it < iters; ++it) {
     const uint32_t tile = tile_of(a.geo, it, bl, G);
     if (it) __syncthreads();
-    if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, a.k > 0 ? &a.st->done : nullptr)) return;
     const uint32_t base = tile << a.geo.TB;
-    if (a.k + 1 < a.m) {
+    if constexpr (kYIn) {
+      const V* yv = reinterpret_cast<const V*>(a.hx);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t s = base | eb | ((uint32_t)r << 6);
+        const bool ok = s < a.geo.D;
+        const V xv = ok ? x[s] : V{(R)0, (R)0};
+        const V yy = ok ? yv[s] : V{(R)0, (R)0};
+        T.xr[r] = xv.x;
+        T.xi[r] = xv.y;
+        T.yr[r] = yy.x;
+        T.yi[r] = yy.y;
+      }
+      if (a.k > 0 && a.st->done) return;
+    } else {
+      if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, a.k > 0 ? &a.st->done : nullptr))
+        return;
+    }
+    if (!kYIn && a.k + 1 < a.m) {
       // y for pass B (the last step has no pass B)
       V* yv = reinterpret_cast<V*>(a.hx);
 #pragma unroll
@@ -324,6 +411,18 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_a(LzBatch B) {
     pass_a_body<R, RB>(B.job[0], blockIdx.x, G);
   } else {
     pass_a_body<R, RB>(B.job[1], blockIdx.x - G, G);
+  }
+}
+
+// Pass A of the reduced basis: y given (complex64 and complex128 with four
+// amplitudes per thread).
+template <typename R>
+__global__ void __launch_bounds__(1024) k_pass_a_y(LzBatch B) {
+  const uint32_t G = B.job[0].geo.grid;
+  if (blockIdx.x < G) {
+    pass_a_body<R, 2, true>(B.job[0], blockIdx.x, G);
+  } else {
+    pass_a_body<R, 2, true>(B.job[1], blockIdx.x - G, G);
   }
 }
 
@@ -579,7 +678,7 @@ __global__ void __launch_bounds__(kStreamBlock)
     k_bracket(HvArgs a, uint32_t D, const typename VT<R>::T* __restrict__ lam,
               const typename VT<R>::T* __restrict__ psi, double cr, double ci,
               const double* beta_dev, KState* st, cplx_d* partials, double* grad_slot,
-              int accumulate) {
+              int accumulate, const uint32_t* __restrict__ pe_reps) {
   using V = typename VT<R>::T;
   constexpr int E = RedChunk<R>::n;
   __shared__ cplx_d wacc[(kStreamBlock / 64) * kMaxScal];
@@ -601,7 +700,9 @@ __global__ void __launch_bounds__(kStreamBlock)
     for (int e = 0; e < E; ++e) {
       const uint32_t s = base + e * T + tid;
       // (Hc psi)[s]: S^x flips one bit with amplitude 1/2; sum of S^z is diagonal
-      const double hc = (a.hc_kind == 0) ? 0.5 : 0.5 * a.sz_count - (double)__popc(s & a.sz_mask);
+      // (in the reduced basis, of the orbit label's bit pattern)
+      const uint32_t pat = pe_reps ? ((s < D) ? pe_reps[s] : 0u) : s;
+      const double hc = (a.hc_kind == 0) ? 0.5 : 0.5 * a.sz_count - (double)__popc(pat & a.sz_mask);
       const double pr = hc * (double)p[e].x, pi = hc * (double)p[e].y;
       const double lr = l[e].x, li = l[e].y;
       sr += lr * pr + li * pi;
@@ -700,6 +801,17 @@ hipError_t launch_hv_t(const HvArgs& a, const Geo& g, const void* v, void* w, hi
 }
 
 template <typename R>
+hipError_t launch_hv_pe_t(const HvArgs& a, const PeArgs& p, const void* v, void* w, hipStream_t s) {
+  using V = typename VT<R>::T;
+  uint32_t blocks = (p.dim + 255u) / 256u;
+  if (blocks > 8192u) blocks = 8192u;   // grid-stride beyond
+  if (blocks < 1u) blocks = 1u;
+  hipLaunchKernelGGL((k_hv_pe<R>), dim3(blocks), dim3(256), 0, s, a, p, reinterpret_cast<const V*>(v),
+                     reinterpret_cast<V*>(w));
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_hv_r(const HvArgs& a, const Geo& g, const void* v, void* w, hipStream_t s) {
   switch (g.RB) {
     case 0: return launch_hv_t<R, 0>(a, g, v, w, s);
@@ -767,8 +879,25 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
       lb.job[j].i0 = i0;
     }
     const int nwin = k - i0 + 1;
+    if (c0.pe) {
+      // reduced basis: y = H v_k by the gather kernel, then pass A on the given y
+      for (int j = 0; j < n; ++j) {
+        const char* xk = (k == 0) ? static_cast<const char*>(calls[j].v_in)
+                                  : static_cast<const char*>(wss[j]->basis) +
+                                        (size_t)(k - 1) * c0.geo.D * sizeof(V);
+        if ((e = launch_hv_pe_t<R>(lb.job[j].hv, *calls[j].pe, xk, wss[j]->hx, s)) != hipSuccess)
+          return e;
+      }
+    }
     if (prof) profiler_start(prof, s);
-    if ((e = launch_pass_r<R>(true, lb, n, s)) != hipSuccess) return e;
+    if (c0.pe) {
+      const Geo& g = c0.geo;
+      const size_t red = ((size_t)1 << g.WB) * kMaxScal * sizeof(cplx_d);
+      hipLaunchKernelGGL((k_pass_a_y<R>), dim3(g.grid * n), dim3(64 << g.WB), red, s, lb);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if ((e = launch_pass_r<R>(true, lb, n, s)) != hipSuccess) {
+      return e;
+    }
     // algorithmic bytes: the window vectors (v_k included) are read once and
     // y = H v_k is written (not in the last step)
     if (prof) profiler_stop(prof, s, kProfPassA, (nwin + (last ? 0 : 1)) * vb);
@@ -811,6 +940,11 @@ hipError_t launch_hv(int prec, const HvArgs& a, const Geo& g, const void* v, voi
   return prec == 0 ? launch_hv_r<double>(a, g, v, w, s) : launch_hv_r<float>(a, g, v, w, s);
 }
 
+hipError_t launch_hv_pe(int prec, const HvArgs& a, const PeArgs& p, const void* v, void* w,
+                        hipStream_t s) {
+  return prec == 0 ? launch_hv_pe_t<double>(a, p, v, w, s) : launch_hv_pe_t<float>(a, p, v, w, s);
+}
+
 hipError_t launch_krylov(const KrylovCall& c, const Workspace& ws, hipStream_t s) {
   const Workspace* w[1] = {&ws};
   return c.prec == 0 ? launch_krylov_t<double>(&c, w, 1, s) : launch_krylov_t<float>(&c, w, 1, s);
@@ -848,17 +982,18 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
 
 hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam, const void* psi,
                           double dt, const double* beta_dev, const Workspace& ws, double* grad_slot,
-                          hipStream_t s, bool accumulate, double coef_im) {
+                          hipStream_t s, bool accumulate, double coef_im,
+                          const uint32_t* pe_reps) {
   const int grid = reduce_grid(D, prec);
   const int acc = accumulate ? 1 : 0;
   if (prec == 0) {
     hipLaunchKernelGGL(k_bracket<double>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const double2*>(lam), reinterpret_cast<const double2*>(psi),
-                       dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc);
+                       dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc, pe_reps);
   } else {
     hipLaunchKernelGGL(k_bracket<float>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const float2*>(lam), reinterpret_cast<const float2*>(psi),
-                       dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc);
+                       dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc, pe_reps);
   }
   return hipGetLastError();
 }

@@ -115,3 +115,20 @@ def test_gradient_equals_full_space_gradient():
 def test_control_sites_must_be_mirror_symmetric():
     with pytest.raises(ValueError):
         pe.PEChain(6, 3, 1.0, 0.5, 1)
+
+
+@pytest.mark.parametrize("LK,D", sorted(workloads.PAPER_PE_DIMS.items()))
+def test_dimensions_quoted_in_the_results(LK, D):
+    """Sec. III.B quotes D = 10, 19, 44, 60, 146; each is the even-orbit count of a
+    K = 3 sector (the (L, K) pairs are the workloads' reading)."""
+    assert pe.sector_dim_count(*LK) == D
+    assert pe.PEBasis(*LK).dim == D
+
+
+def test_row_spot_check_equals_the_whole_product():
+    B = pe.PEBasis(9, 4)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(B.dim) + 1j * rng.standard_normal(B.dim)
+    y = pe.apply_h_pe(B, 2.0, 0.5, EDGES(9), 0.3, x)
+    rows = [0, 5, B.dim // 2, B.dim - 1]
+    assert np.abs(pe.apply_h_pe_rows(B, 2.0, 0.5, EDGES(9), 0.3, x, rows) - y[rows]).max() < 1e-14

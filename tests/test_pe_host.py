@@ -1,0 +1,125 @@
+"""The reduced-basis tables written by the library on the host (kg_pe_tables_host,
+no device) against the oracle's orbit basis, and host-side validation of the
+reduced-basis entry points."""
+
+import ctypes
+import os
+from math import comb
+
+import numpy as np
+import pytest
+
+import workloads
+from oracle import pe
+from paper_2010_03598_amd import _lib
+
+pytestmark = pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH), reason="libkgrape.so not built")
+
+
+def tables(L, K):
+    from paper_2010_03598_amd.reduced import pe_tables_host
+    return pe_tables_host(L, K)
+
+
+def combinatorial_rank(s, L):
+    zeros = [p for p in range(L) if not (s >> p) & 1]
+    return sum(comb(z, i + 1) for i, z in enumerate(zeros))
+
+
+@pytest.mark.parametrize("L,K", [(2, 0), (2, 1), (2, 2), (3, 1), (5, 0), (5, 5), (6, 3), (7, 3),
+                                 (8, 4), (9, 2), (10, 3), (11, 5), (12, 6), (13, 3), (14, 7)])
+def test_tables_match_the_oracle_basis(L, K):
+    t = tables(L, K)
+    B = pe.PEBasis(L, K)
+    lib = _lib.load()
+    assert lib.kg_pe_dim(L, K) == B.dim
+    assert np.array_equal(t["reps"].astype(np.int64), B.reps)
+    st = pe.sector_states(L, K)
+    ranks = np.array([combinatorial_rank(int(s), L) for s in st])
+    assert np.array_equal(np.sort(ranks), np.arange(comb(L, K)))     # a bijection
+    assert np.array_equal(t["index"][ranks].astype(np.int64), B.index(st))
+    n = np.arange(33)
+    assert all(t["binom"][a, b] == comb(a, b) for a in n for b in n)
+
+
+def test_paper_dimensions():
+    lib = _lib.load()
+    for (L, K), D in workloads.PAPER_PE_DIMS.items():
+        assert lib.kg_pe_dim(L, K) == D
+
+
+def test_large_dimension_formula():
+    """(C(L,K) + palindromes) / 2 at sizes the oracle does not enumerate."""
+    lib = _lib.load()
+    assert lib.kg_pe_dim(25, 12) == (comb(25, 12) + comb(12, 6)) // 2
+    assert lib.kg_pe_dim(26, 13) == comb(26, 13) // 2
+    assert lib.kg_pe_dim(32, 16) == (comb(32, 16) + comb(16, 8)) // 2
+
+
+@pytest.mark.parametrize("L,K", [(1, 0), (33, 3), (8, 9), (8, -1)])
+def test_invalid_shapes(L, K):
+    lib = _lib.load()
+    assert lib.kg_pe_dim(L, K) == 0
+    assert lib.kg_pe_tables_bytes(L, K) == 0
+    assert lib.kg_pe_tables_host(L, K, ctypes.c_void_p(0), 0) == _lib.KG_EINVAL
+
+
+def test_table_buffer_too_small():
+    lib = _lib.load()
+    nb = lib.kg_pe_tables_bytes(8, 4)
+    buf = np.zeros(nb, dtype=np.uint8)
+    st = lib.kg_pe_tables_host(8, 4, ctypes.c_void_p(buf.ctypes.data), nb - 1)
+    assert st == _lib.KG_EWORKSPACE
+
+
+def fake_pe(L=9, K=4, dim=None):
+    lib = _lib.load()
+    return _lib.KgPe(L, K, lib.kg_pe_dim(L, K) if dim is None else dim, 1 << 20)
+
+
+@pytest.mark.parametrize("h,pe_,msg", [
+    (_lib.KgXxz(9, _lib.KG_HC_SX, 2.0, 0.5, 1), None, "S^z control"),
+    (_lib.KgXxz(9, _lib.KG_HC_SZ, 2.0, 0.5, 1), None, "mirror-symmetric"),
+    (_lib.KgXxz(9, _lib.KG_HC_SZ, 2.0, 0.5, 1 | (1 << 7)), None, "mirror-symmetric"),
+    (_lib.KgXxz(8, _lib.KG_HC_SZ, 2.0, 0.5, 1 | (1 << 7)), None, "differs"),
+    (_lib.KgXxz(9, _lib.KG_HC_SZ, 2.0, 0.5, 1 | (1 << 8)), dict(dim=7), "dimension"),
+    (_lib.KgXxz(9, _lib.KG_HC_SZ, 2.0, 0.5, 1 | (1 << 8)), dict(K=10), "K=10"),
+])
+def test_invalid_chain_or_basis(h, pe_, msg):
+    lib = _lib.load()
+    p = fake_pe(**(pe_ or {}))
+    st = lib.xxz_pe_apply(ctypes.byref(h), ctypes.byref(p), 0.1, _lib.KG_C128,
+                          ctypes.c_void_p(256), ctypes.c_void_p(1 << 24), None)
+    assert st == _lib.KG_EINVAL
+    assert msg in _lib.last_error()
+
+
+def test_workspace_sizes_scale_with_dim():
+    lib = _lib.load()
+    p = fake_pe(13, 3)
+    k = _lib.KgKrylov(10, 1, 0.0)
+    a = lib.kg_pe_workspace_bytes(ctypes.byref(p), ctypes.byref(k), _lib.KG_C128, 0)
+    b = lib.kg_pe_workspace_bytes(ctypes.byref(p), ctypes.byref(k), _lib.KG_C64, 0)
+    e = lib.kg_pe_workspace_bytes(ctypes.byref(p), ctypes.byref(k), _lib.KG_C128, 1)
+    assert a > b > 0 and e > a
+    vb = lambda n: (n + 255) // 256 * 256
+    assert e - a == 2 * vb(146 * 16)
+    assert lib.kg_pe_states_bytes(ctypes.byref(p), 40, 0, _lib.KG_C64) == 40 * 146 * 8
+    assert lib.kg_pe_states_bytes(ctypes.byref(p), 40, 10, _lib.KG_C64) == 23 * 146 * 8
+    assert lib.kg_pe_states_bytes(ctypes.byref(p), 40, 41, _lib.KG_C64) == 0
+
+
+def test_gradient_variant_checked():
+    lib = _lib.load()
+    p = fake_pe()
+    h = _lib.KgXxz(9, _lib.KG_HC_SZ, 2.0, 0.5, 1 | (1 << 8))
+    k = _lib.KgKrylov(10, 1, 0.0)
+    v = ctypes.c_void_p(1 << 20)
+    args = [ctypes.byref(h), ctypes.byref(p), v, 4, 0.5, ctypes.byref(k), _lib.KG_C128, v, v, v, v,
+            v, v, 0, 0]
+    assert lib.grape_gradient_pe(*args, 7, 0, v, 1 << 20, None) == _lib.KG_EINVAL
+    assert "variant" in _lib.last_error()
+    assert lib.grape_gradient_pe(*args, _lib.KG_GRAD_ZEROTH, 3, v, 1 << 20, None) == _lib.KG_EINVAL
+    assert "nodes" in _lib.last_error()
+    assert lib.grape_gradient_pe(*args, _lib.KG_GRAD_QUADRATURE, 0, v, 1 << 20, None) == _lib.KG_EINVAL
+    assert "nodes" in _lib.last_error()

@@ -17,6 +17,9 @@ Workloads (all open XXZ chains, J = 1, control operator S^x on site 1):
 * ``adjoint`` L=20, D=1,048,576,  N=400, dt=0.05, m=20, complex64 + FP64 scalars
 * ``batched`` 64 chains, L in 10..16, N in 50..300, dt=0.05, complex64
 * ``large``   L=24, D=16,777,216, N=500, dt=0.05, m=24, complex64 and complex128
+* ``pe_task`` the transfer task of Sec. III.A in the fixed-excitation, even-parity
+  basis (J=2, Delta=0.5, S^z control on sites 1 and L, dt=0.5, m=10);
+  ``pe_large`` is L=25, K=12, N=200, dt=0.1
 
 Random draws use ``numpy.random.default_rng(seed)``: first the controls, then
 the phases of psi0, then the phases of the target, each phase vector
@@ -156,6 +159,63 @@ def batched(seed: int = 3, n_chains: int = 64, m: int = 16) -> List[Chain]:
         chains.append(Chain(L=L, J=1.0, Delta=Delta, hc_kind=HC_SX, hc_sites=1, N=N, dt=0.05,
                             m=m, u=u, psi0=psi0, target=target))
     return chains
+
+
+# ---------------------------------------------------------------- reduced basis
+
+# Dimensions of the fixed-excitation, even-parity spaces studied in Sec. III.B
+# (the figures quote D = 10, 19, 44, 60 and 146).  The (L, K) that give them
+# with K = 3 excitations are this module's reading; the paper names D only.
+PAPER_PE_DIMS = {(6, 3): 10, (7, 3): 19, (9, 3): 44, (10, 3): 60, (13, 3): 146}
+
+
+@dataclasses.dataclass(frozen=True)
+class PETask:
+    """The transfer task e_1 -> e_D of Sec. III.A in the reduced basis of L spins
+    with K excitations: the paper's drift (J_p = 1, alpha_z = 0.5, i.e. J = 2 and
+    Delta = 0.5 in the S = sigma/2 form) and control J_p (S^z_1 + S^z_L).
+
+    e1_state / eD_state are the product states (full-space indices) whose
+    orbits are the task's basis vectors: K up spins in the middle of the chain,
+    and K up spins at the left edge (its orbit also holds the right edge)."""
+
+    L: int
+    K: int
+    J: float
+    Delta: float
+    hc_sites: int
+    N: int
+    dt: float
+    m: int
+    u: np.ndarray
+    e1_state: int
+    eD_state: int
+
+
+def pe_task(L: int, K: int, N: int, seed: int = 5, dt: float = 0.5, m: int = 10) -> PETask:
+    """Controls U(-1, 1) for N slices (the paper draws M = 4D of them), dt = 0.5,
+    Krylov dimension 10 (Sec. III.B)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-1.0, 1.0, N)
+    left = (L - K) // 2
+    e1 = basis_index("d" * left + "u" * K + "d" * (L - K - left))
+    eD = basis_index("u" * K + "d" * (L - K))
+    return PETask(L=L, K=K, J=2.0, Delta=0.5, hc_sites=1 | (1 << (L - 1)), N=N, dt=dt, m=m,
+                  u=u, e1_state=e1, eD_state=eD)
+
+
+def pe_paper(L: int, K: int, seed: int = 5) -> PETask:
+    """A task of Sec. III.B at its own size: M = 4D slices."""
+    return pe_task(L, K, 4 * PAPER_PE_DIMS[(L, K)], seed)
+
+
+def pe_large(seed: int = 6, N: int = 200) -> PETask:
+    """The transport task (odd L, even K) at L = 25, K = 12, N = 200 slices of
+    dt = 0.1.  The spectral radius of this sector is about 20, so dt = 0.5 with
+    10 Krylov vectors would sit outside the step sizes where the truncated
+    propagator is accurate (the control window shrinks with D, Sec. III.B);
+    dt = 0.1 keeps ||H|| dt near 2."""
+    return pe_task(25, 12, N, seed, dt=0.1)
 
 
 def scaled(chain: Chain, **changes) -> Chain:
