@@ -119,6 +119,102 @@ def time_hv(kg, torch, L, dtype, reps=50):
             "launches": reps, "timing": "HIP graph of the launches, best of 3 replays"}
 
 
+def time_pe(kg, torch, workloads, steps=2, reps=20):
+    """The reduced basis on the transport task at L=25, K=12 (2,600,612
+    amplitudes), N=200 slices of dt=0.1, m=10: centred gradients (the paper's
+    production variant) in complex64 + FP64 scalars, timed over `steps`
+    evaluations with sampled kernel timing, one FP64 evaluation for the error,
+    and the gather H v alone in a HIP graph."""
+    import numpy as np
+    t = workloads.pe_large()
+    B = kg.ReducedBasis(t.L, t.K)
+    tab = kg.pe_tables_host(t.L, t.K)
+    h = kg.XXZ(t.L, t.J, t.Delta, kg.KG_HC_SZ, t.hc_sites)
+    k = kg.Krylov(t.m)
+    ckpt = 14
+    u = torch.tensor(t.u, dtype=torch.float64, device="cuda")
+
+    def unit(state):
+        e = np.zeros(B.dim, dtype=np.complex128)
+        rev = int(format(state, f"0{t.L}b")[::-1], 2)
+        e[int(np.searchsorted(tab["reps"], min(state, rev)))] = 1.0
+        return e
+
+    e1, eD = unit(t.e1_state), unit(t.eD_state)
+    res = {}
+    for dtype, n in ((torch.complex64, steps), (torch.complex128, 1)):
+        psi0 = torch.tensor(e1, dtype=dtype, device="cuda")
+        f = torch.tensor(eD, dtype=dtype, device="cuda")
+        ws = kg.ReducedWorkspace(B, k, dtype)
+        states = kg.pe_states(B, t.N, ckpt, dtype)
+        run = lambda: kg.grape_gradient_pe(h, B, u, t.dt, k, psi0, f, ckpt_every=ckpt,
+                                           variant="centred", states=states, workspace=ws)
+        r = run()
+        torch.cuda.synchronize()
+        prof = kg.profile(sample_every=8, max_launches=max(1024, n * 20000)) \
+            if dtype == torch.complex64 else None
+        if prof:
+            prof.__enter__()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            r = run()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if prof:
+            prof.__exit__(None, None, None)
+        res[dtype] = ((t1 - t0) / n, float(r.F.cpu()), r.grad.cpu().numpy(),
+                      prof.result if prof else None)
+        log(f"reduced basis: {n} centred gradients ({dtype}) in {t1 - t0:.3f} s")
+        del ws, states
+    sec, F64, g64, prof = res[torch.complex64]
+    _, F128, g128, _ = res[torch.complex128]
+    # the gather H v alone
+    x = torch.tensor(workloads.random_state(np.random.default_rng(3), B.dim), dtype=torch.complex64,
+                     device="cuda")
+    y = torch.empty_like(x)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            kg.xxz_pe_apply(h, B, 0.3, x, out=y)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for _ in range(reps):
+            kg.xxz_pe_apply(h, B, 0.3, x, out=y)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(3):
+        e0.record()
+        graph.replay()
+        e1_.record()
+        e1_.synchronize()
+        best = min(best, e0.elapsed_time(e1_) * 1e-3 / reps)
+    hv_bytes = B.dim * (2 * x.element_size() + 8)   # x read, y written, labels and ranks read
+    kern = {c: {"launches_timed": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
+                "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+            for c, v in prof.items() if v["launches"]}
+    return {"metric": "reduced-basis centred gradient evals/s", "value": 1.0 / sec,
+            "unit": "gradient evals/s", "ms_per_step": sec * 1e3, "steps": steps,
+            "workload": f"e_1 -> e_D transport, L={t.L}, K={t.K}, dim={B.dim}, N={t.N}, "
+                        f"dt={t.dt}, m={t.m} full reorth, ckpt every {ckpt}, seed 6",
+            "precision": "complex64 vectors, FP64 scalars",
+            "mixed_vs_fp64_error": {"F_rel": abs(F64 - F128) / abs(F128),
+                                    "grad_rel_l2": float(np.linalg.norm(g64 - g128) /
+                                                         np.linalg.norm(g128)),
+                                    "F_fp64": F128},
+            "fp64_ms_per_step": res[torch.complex128][0] * 1e3,
+            "kernels": kern,
+            "hv_pe": {"us_per_launch": best * 1e6, "algorithmic_bytes": hv_bytes,
+                      "algorithmic_GBps": hv_bytes / best / 1e9,
+                      "frac_of_peak": hv_bytes / best / 1e9 / HBM_PEAK_GBS,
+                      "timing": "HIP graph of the launches, best of 3 replays"}}
+
+
 def time_batched(kg, torch, workloads, steps=3, fp64=True):
     """The batched form on the 64-chain workload (L in 10..16, N in 50..300): the
     autotuned persistent launch (complex64 vectors, FP64 scalars; m per chain from
@@ -260,6 +356,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-pe", action="store_true", help="skip the reduced-basis leg")
+    ap.add_argument("--only-pe", action="store_true",
+                    help="run only the reduced-basis leg (--steps evaluations) and print its JSON")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -285,6 +384,9 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only_pe:
+        print(json.dumps(time_pe(kg, torch, workloads, steps=args.steps)), flush=True)
+        return
     c = workloads.adjoint()
     ckpt = workloads.ADJOINT_CKPT_EVERY
     log(f"workload: L={c.L} N={c.N} m={c.m} dt={c.dt} Delta={c.Delta} ckpt_every={ckpt}")
@@ -323,6 +425,9 @@ def main():
     bat = None if args.no_batched else time_batched(kg, torch, workloads)
     if bat:
         log(f"batched: {bat['value']:.1f} chain gradient evals/s")
+    pe = None if args.no_pe else time_pe(kg, torch, workloads)
+    if pe:
+        log(f"reduced basis: {pe['value']:.2f} gradient evals/s")
     cpu = None if args.no_cpu else cpu_baseline(c, args.cpu_budget)
 
     out = {
@@ -356,6 +461,7 @@ def main():
                      "sampled_launches": d["launches"]},
         "kernels": classes,
         "batched": bat,
+        "reduced_basis": pe,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -262,13 +262,14 @@ int64_t kg_pe_dim(int32_t L, int32_t K);
 /* Bytes of device tables of the basis (0 for invalid arguments). */
 size_t kg_pe_tables_bytes(int32_t L, int32_t K);
 
-/* The tables in HOST memory (no device call), kg_pe_tables_bytes long:
- *   byte 0:          binomial coefficients C(n, k), uint32 at [n * 33 + k], n, k <= 32;
- *   byte 4608:       the orbit labels, uint32, dim of them, ascending;
- *   byte 4608 + R:   (R = 4 dim rounded up to a multiple of 256) the orbit
- *                    index (int32) of every sector pattern s at its
- *                    combinatorial rank sum_i C(z_i, i) over the zero-bit
- *                    positions z_1 < z_2 < ... of s (C(L, K) entries).
+/* The tables in HOST memory (no device call), kg_pe_tables_bytes long, with
+ * R = 4 dim rounded up to a multiple of 256:
+ *   byte 0:            binomial coefficients C(n, k), uint32 at [n * 33 + k], n, k <= 32;
+ *   byte 4608:         the orbit labels, uint32, dim of them, ascending;
+ *   byte 4608 + R:     the combinatorial rank of each label (uint32, dim);
+ *   byte 4608 + 2 R:   the orbit index (int32) of every sector pattern s at
+ *                      its combinatorial rank sum_i C(z_i, i) over the zero-bit
+ *                      positions z_1 < z_2 < ... of s (C(L, K) entries).
  * A caller may copy this image to device memory itself and fill a kg_pe with
  * it.  Errors: KG_EINVAL, KG_EWORKSPACE. */
 kg_status kg_pe_tables_host(int32_t L, int32_t K, void* tables_host, size_t tables_bytes);

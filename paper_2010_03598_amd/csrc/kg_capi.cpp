@@ -874,16 +874,17 @@ int64_t pe_dim(int L, int K) {
 }
 
 // Table layout in the caller's buffer: binomials (uint32, kPeBinom^2), orbit
-// representatives (uint32, dim), index by combinatorial rank (int32, C(L,K)),
-// each at a 256-byte boundary.
+// representatives (uint32, dim), their ranks (uint32, dim), index by
+// combinatorial rank (int32, C(L,K)), each at a 256-byte boundary.
 struct PeLayout {
-  size_t off_reps, off_index, total;
+  size_t off_reps, off_ranks, off_index, total;
 };
 
 PeLayout pe_layout(int L, int K) {
   PeLayout o;
   o.off_reps = align_up(sizeof(uint32_t) * kPeBinom * kPeBinom, 256);
-  o.off_index = o.off_reps + align_up(sizeof(uint32_t) * (size_t)pe_dim(L, K), 256);
+  o.off_ranks = o.off_reps + align_up(sizeof(uint32_t) * (size_t)pe_dim(L, K), 256);
+  o.off_index = o.off_ranks + align_up(sizeof(uint32_t) * (size_t)pe_dim(L, K), 256);
   o.total = o.off_index + align_up(sizeof(int32_t) * (size_t)pascal().c[L][K], 256);
   return o;
 }
@@ -927,6 +928,7 @@ PeArgs pe_args(const kg_pe* pe) {
   memset(&a, 0, sizeof(a));
   a.binom = reinterpret_cast<const uint32_t*>(t);
   a.reps = reinterpret_cast<const uint32_t*>(t + o.off_reps);
+  a.ranks = reinterpret_cast<const uint32_t*>(t + o.off_ranks);
   a.index = reinterpret_cast<const int32_t*>(t + o.off_index);
   a.L = pe->L;
   a.K = pe->K;
@@ -985,6 +987,7 @@ kg_status kg_pe_tables_host(int32_t L, int32_t K, void* tables_host, size_t tabl
   for (int n = 0; n < kPeBinom; ++n)
     for (int k = 0; k < kPeBinom; ++k) binom[n * kPeBinom + k] = (uint32_t)P.c[n][k];
   uint32_t* reps = reinterpret_cast<uint32_t*>(host + o.off_reps);
+  uint32_t* ranks = reinterpret_cast<uint32_t*>(host + o.off_ranks);
   int32_t* index = reinterpret_cast<int32_t*>(host + o.off_index);
   const uint64_t full = (L == 32) ? 0xFFFFFFFFull : ((1ull << L) - 1ull);
   auto rank = [&](uint32_t s) {
@@ -1004,6 +1007,7 @@ kg_status kg_pe_tables_host(int32_t L, int32_t K, void* tables_host, size_t tabl
     const uint64_t rk = rank(s);
     if (s <= rs) {
       reps[next] = s;
+      ranks[next] = (uint32_t)rk;
       index[rk] = (int32_t)next;
       ++next;
     } else {

@@ -92,6 +92,7 @@ hipError_t launch_hv(int prec, const HvArgs& a, const Geo& g, const void* v, voi
 // The fixed-excitation, parity-even basis (device tables built by kg_pe_build).
 struct PeArgs {
   const uint32_t* reps;    // orbit representatives (bit patterns), ascending
+  const uint32_t* ranks;   // combinatorial rank of each representative
   const int32_t* index;    // basis index of a sector state's orbit, by combinatorial rank
   const uint32_t* binom;   // C(n, k) at [n * kPeBinom + k], n, k <= 32
   int32_t L, K;

@@ -96,59 +96,80 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_hv(HvArgs a, Geo g, co
 // rank(s) = sum_i C(z_i, i) for zero positions z_1 < z_2 < ...; exchanging a
 // zero at p with a one at p+1 (or back) changes the rank by C(p, j) with j the
 // zeros below p.  The S^z control is diagonal; the amplitudes x_a are gathered.
+//
+// The gathers are latency-bound (index, then amplitude, per bond), so the
+// bonds of a row go kPeHops at a time: their ranks first, then all index
+// loads, then all amplitude loads, each group in flight together.  Slots past
+// a row's last bond load the row's own entries (cached) with weight 0.  The
+// binomial table is staged in LDS; the label's own rank comes from the tables.
+constexpr int kPeHops = 8;
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_hv_pe(HvArgs a, PeArgs p,
                                                const typename VT<R>::T* __restrict__ x,
                                                typename VT<R>::T* __restrict__ y) {
   using V = typename VT<R>::T;
+  __shared__ uint32_t sb[kPeBinom * kPeBinom];
+  for (int i = threadIdx.x; i < kPeBinom * kPeBinom; i += blockDim.x) sb[i] = p.binom[i];
+  __syncthreads();
   const int L = p.L;
   const uint32_t full = (L == 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
   const uint32_t bondmask = (L >= 2) ? ((1u << (L - 1)) - 1u) : 0u;
   const double u = control_value(a);
   const R hJ = (R)a.half_J, czz = (R)a.c_zz, uR = (R)u;
   const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
-  for (uint32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < p.dim;
-       b += gridDim.x * blockDim.x) {
+  uint32_t lo = 0, hi = p.dim, b0 = blockIdx.x * blockDim.x + threadIdx.x,
+           stride = gridDim.x * blockDim.x;
+  if ((gridDim.x & 7u) == 0u) {
+    // contiguous rows per XCD (blocks are dealt to the 8 XCDs round robin)
+    const uint32_t chunk = (p.dim + 7u) >> 3;
+    lo = (blockIdx.x & 7u) * chunk;
+    hi = min(lo + chunk, p.dim);
+    b0 = lo + (blockIdx.x >> 3) * blockDim.x + threadIdx.x;
+    stride = (gridDim.x >> 3) * blockDim.x;
+  }
+  for (uint32_t b = b0; b < hi; b += stride) {
     const uint32_t r = p.reps[b];
+    const uint32_t rank = p.ranks[b];
+    const uint32_t zeros = ~r & full;
     const bool nb2 = (__brev(r) >> (32 - L)) != r;
     const int n_anti = (int)__popc((r ^ (r >> 1)) & bondmask);   // __popc is unsigned
     R d = czz * (R)(L - 1 - 2 * n_anti);
     if (a.hc_kind == 1) d += uR * ((R)(0.5 * a.sz_count) - (R)__popc(r & a.sz_mask));
     const V xb = x[b];
     R yr = d * xb.x, yi = d * xb.y;
-    uint32_t rank = 0;
-    {
-      uint32_t z = ~r & full;
-      int i = 1;
-      while (z) {
-        rank += p.binom[__builtin_ctz(z) * kPeBinom + i];
-        ++i;
-        z &= z - 1u;
-      }
-    }
-    uint32_t act = (r ^ (r >> 1)) & bondmask;
+    bool bad = rank >= p.nsec;
+    uint32_t act = bad ? 0u : ((r ^ (r >> 1)) & bondmask);
     while (act) {
-      const int q = __builtin_ctz(act);
-      act &= act - 1u;
-      const uint32_t s2 = r ^ (3u << q);
-      const int below = __popc(~r & full & ((1u << q) - 1u));
-      const uint32_t dl = p.binom[q * kPeBinom + below];
-      const uint32_t rk = (((r >> q) & 1u) == 0u) ? rank + dl : rank - dl;
-      const bool na2 = (__brev(s2) >> (32 - L)) != s2;
-      const R w = (nb2 == na2) ? (R)1 : (nb2 ? rt2 : irt2);
+      uint32_t rk[kPeHops];
+      R w[kPeHops];
+#pragma unroll
+      for (int j = 0; j < kPeHops; ++j) {
+        const bool on = act != 0u;
+        const int q = on ? __builtin_ctz(act) : 0;
+        act &= act - 1u;
+        const uint32_t dl = sb[q * kPeBinom + __popc(zeros & ((1u << q) - 1u))];
+        const uint32_t s2 = r ^ (3u << q);
+        const bool na2 = (__brev(s2) >> (32 - L)) != s2;
+        rk[j] = on ? ((((r >> q) & 1u) == 0u) ? rank + dl : rank - dl) : rank;
+        w[j] = on ? ((nb2 == na2) ? (R)1 : (nb2 ? rt2 : irt2)) : (R)0;
+      }
+      int32_t ai[kPeHops];
+#pragma unroll
+      for (int j = 0; j < kPeHops; ++j) ai[j] = (rk[j] < p.nsec) ? p.index[rk[j]] : -1;
       // tables live in caller memory: an entry out of range gives NaN, never a stray load
-      const int32_t ai = (rk < p.nsec) ? p.index[rk] : -1;
-      if ((uint32_t)ai < p.dim) {
-        const V xa = x[ai];
-        yr += hJ * w * xa.x;
-        yi += hJ * w * xa.y;
-      } else {
-        yr = yi = (R)NAN;
+#pragma unroll
+      for (int j = 0; j < kPeHops; ++j) {
+        const bool ok = (uint32_t)ai[j] < p.dim;
+        bad = bad || !ok;
+        const V xa = x[ok ? (uint32_t)ai[j] : b];
+        yr += hJ * w[j] * xa.x;
+        yi += hJ * w[j] * xa.y;
       }
     }
     V o;
-    o.x = yr;
-    o.y = yi;
+    o.x = bad ? (R)NAN : yr;
+    o.y = bad ? (R)NAN : yi;
     y[b] = o;
   }
 }
@@ -804,8 +825,9 @@ template <typename R>
 hipError_t launch_hv_pe_t(const HvArgs& a, const PeArgs& p, const void* v, void* w, hipStream_t s) {
   using V = typename VT<R>::T;
   uint32_t blocks = (p.dim + 255u) / 256u;
-  if (blocks > 8192u) blocks = 8192u;   // grid-stride beyond
+  if (blocks > 2048u) blocks = 2048u;   // grid-stride beyond (the binomials are staged per block)
   if (blocks < 1u) blocks = 1u;
+  if (blocks >= 64u) blocks = (blocks + 7u) & ~7u;
   hipLaunchKernelGGL((k_hv_pe<R>), dim3(blocks), dim3(256), 0, s, a, p, reinterpret_cast<const V*>(v),
                      reinterpret_cast<V*>(w));
   return hipGetLastError();
@@ -881,6 +903,7 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     const int nwin = k - i0 + 1;
     if (c0.pe) {
       // reduced basis: y = H v_k by the gather kernel, then pass A on the given y
+      if (prof) profiler_start(prof, s);
       for (int j = 0; j < n; ++j) {
         const char* xk = (k == 0) ? static_cast<const char*>(calls[j].v_in)
                                   : static_cast<const char*>(wss[j]->basis) +
@@ -888,6 +911,8 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
         if ((e = launch_hv_pe_t<R>(lb.job[j].hv, *calls[j].pe, xk, wss[j]->hx, s)) != hipSuccess)
           return e;
       }
+      // x read, y written, and the orbit label and rank of every output read
+      if (prof) profiler_stop(prof, s, kProfHv, vb * 2.0 + (double)c0.geo.D * 8.0 * n);
     }
     if (prof) profiler_start(prof, s);
     if (c0.pe) {

@@ -24,7 +24,7 @@ def pe_dim(L: int, K: int) -> int:
 
 def pe_tables_host(L: int, K: int) -> dict:
     """The tables as kg_pe_tables_host writes them (host memory, no device):
-    binom (33 x 33), reps (dim,), index (C(L, K),)."""
+    binom (33 x 33), reps (dim,), ranks (dim,), index (C(L, K),)."""
     lib = _lib.load()
     nb = int(lib.kg_pe_tables_bytes(int(L), int(K)))
     if nb == 0:
@@ -34,10 +34,13 @@ def pe_tables_host(L: int, K: int) -> dict:
         int(L), int(K), ctypes.c_void_p(buf.ctypes.data), nb))
     dim = pe_dim(L, K)
     off_reps = 4608
-    off_index = off_reps + (4 * dim + 255) // 256 * 256
+    R = (4 * dim + 255) // 256 * 256
+    off_ranks = off_reps + R
+    off_index = off_ranks + R
     from math import comb
     return {"binom": buf[:4 * 33 * 33].view(np.uint32).reshape(33, 33),
             "reps": buf[off_reps:off_reps + 4 * dim].view(np.uint32),
+            "ranks": buf[off_ranks:off_ranks + 4 * dim].view(np.uint32),
             "index": buf[off_index:off_index + 4 * comb(L, K)].view(np.int32)}
 
 

@@ -38,6 +38,7 @@ def test_tables_match_the_oracle_basis(L, K):
     ranks = np.array([combinatorial_rank(int(s), L) for s in st])
     assert np.array_equal(np.sort(ranks), np.arange(comb(L, K)))     # a bijection
     assert np.array_equal(t["index"][ranks].astype(np.int64), B.index(st))
+    assert np.array_equal(t["ranks"], [combinatorial_rank(int(r), L) for r in B.reps])
     n = np.arange(33)
     assert all(t["binom"][a, b] == comb(a, b) for a in n for b in n)
 
