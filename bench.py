@@ -215,6 +215,44 @@ def time_pe(kg, torch, workloads, steps=2, reps=20):
                       "timing": "HIP graph of the launches, best of 3 replays"}}
 
 
+def fig2b(kg, torch, workloads, sizes, max_iter=300):
+    """Run-time study of the transfer task (Fig. 2): for each (L, K), L-BFGS on
+    centred GPU gradients in the reduced basis (complex128, each evaluation
+    replayed from a captured HIP graph) from controls U(-1, 1) with M = 4D
+    slices, dt = 0.5, m = 10 to I <= 1e-2.  Reports the total run time R, the
+    iterations, and the elementary run time R~ = R / (iterations * M)."""
+    import numpy as np
+    from paper_2010_03598_amd import optimize
+    rows = []
+    for L, K in sizes:
+        dim = kg.pe_dim(L, K)
+        t = workloads.pe_task(L, K, 4 * dim, seed=5)
+        B = kg.ReducedBasis(L, K)
+        tab = kg.pe_tables_host(L, K)
+
+        def unit(state):
+            e = np.zeros(dim, dtype=np.complex128)
+            rev = int(format(state, f"0{L}b")[::-1], 2)
+            e[int(np.searchsorted(tab["reps"], min(state, rev)))] = 1.0
+            return e
+
+        psi0 = torch.tensor(unit(t.e1_state), device="cuda")
+        f = torch.tensor(unit(t.eD_state), device="cuda")
+        h = kg.XXZ(L, t.J, t.Delta, kg.KG_HC_SZ, t.hc_sites)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = optimize.optimize_controls(h, t.u, t.dt, kg.Krylov(t.m), psi0, f, I_target=1e-2,
+                                         max_iter=max_iter, basis=B, graph=True)
+        R = time.perf_counter() - t0
+        row = {"L": L, "K": K, "D": dim, "M": t.N, "iterations": res.iterations,
+               "evaluations": res.evaluations, "reason": res.reason, "I_final": res.f,
+               "R_s": R, "R_tilde_us": R / max(res.iterations, 1) / t.N * 1e6,
+               "s_per_evaluation": R / res.evaluations}
+        log(json.dumps(row))
+        rows.append(row)
+    return rows
+
+
 def time_batched(kg, torch, workloads, steps=3, fp64=True):
     """The batched form on the 64-chain workload (L in 10..16, N in 50..300): the
     autotuned persistent launch (complex64 vectors, FP64 scalars; m per chain from
@@ -359,6 +397,8 @@ def main():
     ap.add_argument("--no-pe", action="store_true", help="skip the reduced-basis leg")
     ap.add_argument("--only-pe", action="store_true",
                     help="run only the reduced-basis leg (--steps evaluations) and print its JSON")
+    ap.add_argument("--fig2b", type=str, default="", metavar="L:K,L:K,...",
+                    help="run only the optimisation run-time study at these sizes, e.g. 8:4,10:4")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -386,6 +426,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.only_pe:
         print(json.dumps(time_pe(kg, torch, workloads, steps=args.steps)), flush=True)
+        return
+    if args.fig2b:
+        sizes = [tuple(int(v) for v in p.split(":")) for p in args.fig2b.split(",")]
+        print(json.dumps({"study": "transfer-task optimisation run time (Fig. 2)",
+                          "rows": fig2b(kg, torch, workloads, sizes)}), flush=True)
         return
     c = workloads.adjoint()
     ckpt = workloads.ADJOINT_CKPT_EVERY

@@ -17,6 +17,8 @@
  *   grape_gradient_first_order  first order of the hierarchy of the time-averaged
  *                   control operator (one commutator with H_j, App. B)
  *   grape_ascent_update  u <- u + eta g / max|g|            (steepest ascent, Algorithm 1 update)
+ *   grape_gradient_columns  operator control on a block of columns: the gradient of
+ *                   |(1/n) sum_c <w_c|U(T)|psi_c>|^2 (the generalisation named in Sec. IV)
  *   xxz_pe_apply, krylov_expv_pe, grape_forward_pe, grape_gradient_pe
  *                   the same in the basis of fixed excitation number and even
  *                   mirror parity (Sec. III.A), for S^z controls on mirror-symmetric sites
@@ -224,6 +226,35 @@ kg_status grape_gradient_first_order(const kg_xxz* h, const double* u_dev, int32
 kg_status grape_ascent_update(double* u_dev, const double* grad_dev, int32_t N, double eta,
                               void* stream);
 
+/* ---------------------------------------------------------------- operator control
+ * The conclusions name the control of operators (unitaries) as the method's
+ * generalisation.  For a block of n columns psi_c -> w_c (all 2^L basis
+ * vectors and W = the target unitary's columns give the whole gate) the
+ * objective is the phase-insensitive subspace gate fidelity
+ *   F = |beta|^2,  beta = (1/n) sum_c <w_c| U(T) |psi_c>   (= |Tr(W^dag U)/D|^2 for n = D),
+ * and its zeroth-order gradient is Eq. 5 with the brackets of all columns:
+ *   dF/du_j ~ 2 dt Im(conj(beta) (1/n) sum_c <lambda_{c,j}|Hc|psi_{c,j}>),
+ * lambda_{c,N} = w_c propagated backward per column (centred = 1: the bracket
+ * sums averaged over the two ends of each slice, as grape_gradient_centred).
+ * Every column has its own Krylov spaces; the forward sweeps of two columns
+ * share each launch.
+ *   psi0s, targets  n_cols vectors of 2^L amplitudes each, column c at c * 2^L
+ *   states          n_cols state buffers of kg_states_bytes(h, N, ckpt_every, prec)
+ *                   bytes each, column c at c times that size
+ *                   (kg_columns_states_bytes gives the total)
+ *   beta_cols_dev   2 n_cols doubles: <w_c|psi_{c,N}> per column (output)
+ *   F_dev (nullable), beta_dev (2 doubles), grad_dev (N doubles): F, beta, dF/du
+ *   ws              kg_workspace_bytes, as for grape_gradient
+ * Errors: KG_EINVAL, KG_EWORKSPACE, KG_EDEVICE. */
+size_t kg_columns_states_bytes(const kg_xxz* h, int32_t n_cols, int32_t N, int32_t ckpt_every,
+                               int32_t prec);
+kg_status grape_gradient_columns(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                 const kg_krylov* k, int32_t prec, int32_t n_cols,
+                                 const void* psi0s, const void* targets, double* F_dev,
+                                 double* beta_dev, double* beta_cols_dev, double* grad_dev,
+                                 void* states, int32_t ckpt_every, int32_t centred, void* ws,
+                                 size_t ws_bytes, void* stream);
+
 /* ---------------------------------------------------------------- reduced basis
  * Sec. III.A: H0 and an S^z control on a mirror-symmetric set of sites conserve
  * the number K of excitations (up spins, zero bits) and the mirror parity
@@ -320,6 +351,16 @@ kg_status grape_gradient_pe(const kg_xxz* h, const kg_pe* pe, const double* u_de
                             void* states, int32_t ckpt_every, int32_t states_valid,
                             int32_t variant, int32_t nodes, void* ws, size_t ws_bytes,
                             void* stream);
+
+/* Operator control in the reduced basis: grape_gradient_columns with vectors
+ * of pe->dim amplitudes, n_cols state buffers of kg_pe_states_bytes each and
+ * the workspace of kg_pe_workspace_bytes (extended = 0). */
+kg_status grape_gradient_columns_pe(const kg_xxz* h, const kg_pe* pe, const double* u_dev,
+                                    int32_t N, double dt, const kg_krylov* k, int32_t prec,
+                                    int32_t n_cols, const void* psi0s, const void* targets,
+                                    double* F_dev, double* beta_dev, double* beta_cols_dev,
+                                    double* grad_dev, void* states, int32_t ckpt_every,
+                                    int32_t centred, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- batched form
  * Many independent chains (different L, Delta, N, m) evaluated by one

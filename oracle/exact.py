@@ -81,6 +81,30 @@ def exact_gradient_dense(H0, Hc, u, psi0, target, dt, method="dk"):
     return abs(beta) ** 2, g
 
 
+def exact_operator_gradient_dense(H0, Hc, u, psi0s, targets, dt):
+    """F = |(1/n) Tr(W^dag U(T) Psi0)|^2 for the columns psi0s (n, D) and targets
+    (n, D), and dF/du_j = 2 Re(conj(beta) dbeta/du_j) with the exact derivative
+    of U_j (Daleckii-Krein), from dense propagators."""
+    u = np.asarray(u, dtype=np.float64)
+    N = u.shape[0]
+    P0 = np.asarray(psi0s, dtype=np.complex128).T          # D x n
+    W = np.asarray(targets, dtype=np.complex128).T
+    n = P0.shape[1]
+    Us = [propagator(H0 + uj * Hc, dt) for uj in u]
+    fwd = [P0]
+    for U in Us:
+        fwd.append(U @ fwd[-1])
+    beta = np.trace(W.conj().T @ fwd[N]) / n
+    g = np.zeros(N)
+    lam = W
+    for j in range(N, 0, -1):
+        dU = dU_daleckii_krein(H0 + u[j - 1] * Hc, Hc, dt)
+        dbeta = np.trace(lam.conj().T @ dU @ fwd[j - 1]) / n
+        g[j - 1] = 2.0 * (np.conj(beta) * dbeta).real
+        lam = Us[j - 1].conj().T @ lam
+    return abs(beta) ** 2, g
+
+
 def exact_gradient_quadrature(chain, u, psi0, target, dt, m, slices=None, nodes=8,
                               reorth=True):
     """dF/du_j for selected slices by Gauss-Legendre quadrature inside the slice.

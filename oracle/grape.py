@@ -141,6 +141,38 @@ def gradient_hierarchy(chain: Chain, u, psi0, target, dt, m, P, reorth=True,
                       m_eff_bwd=m_bwd)
 
 
+def gradient_columns(chain: Chain, u, psi0s, targets, dt, m, reorth=True, tol=None,
+                     centred=False) -> GradResult:
+    """Operator control on a block of n columns (the generalisation named in the
+    conclusions): the phase-insensitive subspace gate fidelity
+        F = |beta|^2,  beta = (1/n) sum_c <w_c| U(T) |psi_c>,
+    which is |Tr(W^dag U)/D|^2 when the columns are a whole basis.  Its
+    zeroth-order gradient is Eq. 5 with the brackets of all columns summed:
+        dF/du_j ~ 2 dt Im(conj(beta) (1/n) sum_c <lambda_{c,j}|Hc|psi_{c,j}>),
+    lambda_{c,N} = w_c propagated backward per column; `centred` averages the
+    bracket sums at the two ends of each slice as in gradient_centred.
+    psi0s, targets: arrays of shape (n, D)."""
+    u = np.asarray(u, dtype=np.float64)
+    N = u.shape[0]
+    psi0s = np.atleast_2d(np.asarray(psi0s, dtype=np.complex128))
+    targets = np.atleast_2d(np.asarray(targets, dtype=np.complex128))
+    n = psi0s.shape[0]
+    cols = [forward(chain, u, psi0s[c], dt, m, reorth, tol, keep=True)[0] for c in range(n)]
+    beta = sum(overlap(targets[c], cols[c][N]) for c in range(n)) / n
+    G = np.zeros(N + 1, dtype=np.complex128)        # (1/n) sum_c <lambda_c|Hc|psi_c> at j
+    for c in range(n):
+        lam = targets[c].copy()
+        for j in range(N, -1 if centred else 0, -1):
+            G[j] += np.vdot(lam, chain.apply_hc(cols[c][j])) / n
+            if j >= (1 if centred else 2):
+                lam = krylov.expv(lambda v, uj=u[j - 1]: chain.apply(uj, v), lam, -dt, m,
+                                  reorth, tol)
+    g_end = 2.0 * dt * (np.conj(beta) * G).imag
+    g = 0.5 * (g_end[:-1] + g_end[1:]) if centred else g_end[1:]
+    return GradResult(F=abs(beta) ** 2, beta=beta, grad=g, psi_N=np.array([s[N] for s in cols]),
+                      m_eff_fwd=np.zeros(N, dtype=np.int64), m_eff_bwd=np.zeros(N, dtype=np.int64))
+
+
 def ascent_update(u, g, eta):
     """u + eta * g / max|g| (no change when the gradient vanishes)."""
     gmax = float(np.max(np.abs(g)))

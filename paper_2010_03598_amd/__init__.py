@@ -10,7 +10,8 @@ from ._lib import (KG_C64, KG_C128, KG_HC_SX, KG_HC_SZ, KgError, LIB_PATH,  # no
                    load as load_library)
 from .autograd import GrapeFidelity, fidelity  # noqa: F401
 from .api import (XXZ, GrapeResult, Krylov, Workspace, debug_index_map, profile,  # noqa: F401
-                  grape_ascent_update, grape_forward, grape_gradient, krylov_expv, new_states,
+                  grape_ascent_update, grape_forward, grape_gradient, grape_gradient_columns,
+                  krylov_expv, new_states,
                   states_bytes, xxz_apply)
 from .reduced import (ReducedBasis, ReducedWorkspace, grape_forward_pe,  # noqa: F401
                       grape_gradient_pe, krylov_expv_pe, pe_dim, pe_states, pe_tables_host,
@@ -18,6 +19,7 @@ from .reduced import (ReducedBasis, ReducedWorkspace, grape_forward_pe,  # noqa:
 
 __all__ = [
     "XXZ", "Krylov", "Workspace", "GrapeResult", "xxz_apply", "krylov_expv", "grape_forward",
+    "grape_gradient_columns",
     "grape_gradient", "grape_ascent_update", "debug_index_map", "new_states", "states_bytes",
     "KG_C64", "KG_C128", "KG_HC_SX", "KG_HC_SZ", "KgError", "load_library", "LIB_PATH", "profile",
     "GrapeFidelity", "fidelity", "ReducedBasis", "ReducedWorkspace", "pe_dim", "pe_states",

@@ -97,6 +97,11 @@ SIGNATURES = {
     "grape_gradient_batched": (_I32, [_P, _P, _I32, _I32, _P, ctypes.c_int64, _P, _P, ctypes.c_int64,
                                       _P, ctypes.c_int64, _P, _P, _P, _P, _SZ, _P, _P]),
     "kg_profile_end": (_I32, [_P, _P, _P]),
+    "kg_columns_states_bytes": (_SZ, [_PX, _I32, _I32, _I32, _I32]),
+    "grape_gradient_columns": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _I32, _P, _P, _P, _P, _P, _P,
+                                      _P, _I32, _I32, _P, _SZ, _P]),
+    "grape_gradient_columns_pe": (_I32, [_PX, _PPE, _P, _I32, _D, _PK, _I32, _I32, _P, _P, _P, _P,
+                                         _P, _P, _P, _I32, _I32, _P, _SZ, _P]),
     "kg_pe_dim": (ctypes.c_int64, [_I32, _I32]),
     "kg_pe_tables_bytes": (_SZ, [_I32, _I32]),
     "kg_pe_tables_host": (_I32, [_I32, _I32, _P, _SZ]),

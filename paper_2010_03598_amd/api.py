@@ -235,6 +235,66 @@ def grape_gradient(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0: torch.Te
     return GrapeResult(F=F, beta=beta, grad=grad, states=states)
 
 
+@dataclasses.dataclass
+class ColumnsResult:
+    F: torch.Tensor          # () float64, |beta|^2
+    beta: torch.Tensor       # (2,) float64, beta = (1/n) sum_c <w_c|psi_c(T)>
+    beta_cols: torch.Tensor  # (n, 2) float64, <w_c|psi_c(T)> per column
+    grad: torch.Tensor       # (N,) float64, dF/du_j
+    states: torch.Tensor
+
+
+def grape_gradient_columns(h: XXZ, u: torch.Tensor, dt: float, k: Krylov, psi0s: torch.Tensor,
+                           targets: torch.Tensor, ckpt_every: int = 0, centred: bool = False,
+                           basis=None, states: Optional[torch.Tensor] = None,
+                           workspace=None) -> ColumnsResult:
+    """Operator control on a block of columns: F = |(1/n) sum_c <w_c|U(T)|psi_c>|^2
+    and its (zeroth-order or centred) gradient.  psi0s, targets: (n, D)
+    contiguous tensors of one complex dtype (D = 2^L, or the dimension of
+    `basis`, a ReducedBasis)."""
+    dtype = psi0s.dtype
+    prec = prec_of(dtype)
+    if psi0s.dim() != 2 or targets.shape != psi0s.shape or targets.dtype != dtype:
+        raise ValueError("psi0s and targets must be (n, D) tensors of the same dtype")
+    if not (psi0s.is_cuda and targets.is_cuda and psi0s.is_contiguous() and targets.is_contiguous()):
+        raise ValueError("psi0s and targets must be contiguous CUDA/HIP tensors")
+    n, D = psi0s.shape
+    if D != (h.D if basis is None else basis.dim):
+        raise ValueError(f"columns of {D} amplitudes do not match the space")
+    N = u.numel()
+    _f64(u, N, "u")
+    dev = psi0s.device
+    lib = _lib.load()
+    if basis is None:
+        one = states_bytes(h, N, ckpt_every, dtype)
+        ws = _ws(workspace, h, k, dtype, dev)
+    else:
+        from . import reduced
+        one = int(lib.kg_pe_states_bytes(basis.ref(), N, int(ckpt_every), prec))
+        if one == 0:
+            raise ValueError(_lib.last_error())
+        ws = reduced._rws(workspace, basis, k, dtype, dev)
+    esz = 16 if dtype == torch.complex128 else 8
+    if states is None:
+        states = torch.empty(n * one // esz, dtype=dtype, device=dev)
+    elif states.numel() * states.element_size() < n * one:
+        raise ValueError("states buffer too small")
+    F = torch.empty((), dtype=torch.float64, device=dev)
+    beta = torch.empty(2, dtype=torch.float64, device=dev)
+    beta_cols = torch.empty((n, 2), dtype=torch.float64, device=dev)
+    grad = torch.empty(N, dtype=torch.float64, device=dev)
+    common = [N, float(dt), ctypes.byref(k.c()), prec, int(n), _ptr(psi0s), _ptr(targets), _ptr(F),
+              _ptr(beta), _ptr(beta_cols), _ptr(grad), _ptr(states), int(ckpt_every),
+              1 if centred else 0, ws.ptr, ws.nbytes, _stream()]
+    if basis is None:
+        _lib.check("grape_gradient_columns", lib.grape_gradient_columns(
+            ctypes.byref(h.c()), _ptr(u), *common))
+    else:
+        _lib.check("grape_gradient_columns_pe", lib.grape_gradient_columns_pe(
+            ctypes.byref(h.c()), basis.ref(), _ptr(u), *common))
+    return ColumnsResult(F=F, beta=beta, beta_cols=beta_cols, grad=grad, states=states)
+
+
 def grape_ascent_update(u: torch.Tensor, grad: torch.Tensor, eta: float) -> torch.Tensor:
     """u += eta * grad / max|grad| in place, on the device."""
     N = u.numel()

@@ -285,10 +285,16 @@ struct Quadrature {
 // the node states coming from paired Krylov calls on the two workspace slots.
 // With `first_order`, the bracket takes Hc - (i dt/2)[H_j, Hc]: H_j psi_j and
 // H_j lambda_j go to the node vectors and two more brackets are added.
+//
+// Operator control runs one such sweep per column (col = 0..ncols-1): every
+// bracket is scaled by 1/ncols, columns after the first add to the gradient,
+// and the centred average is taken once, after the last column.
 kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta_dev,
                          double* grad_dev, bool centred = false, const Quadrature* Q = nullptr,
-                         bool first_order = false) {
+                         bool first_order = false, int col = 0, int ncols = 1) {
   const HvArgs hc = make_hv(a.h, nullptr, 0.0);
+  const double dt_b = a.dt / ncols;
+  const bool acc = col > 0;
   const uint32_t* pe_reps = a.pe ? a.pe->reps : nullptr;
   const void* lam = a.target;
   for (int q = S.nseg - 1; q >= 0; --q) {
@@ -313,8 +319,8 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
       } else {
         Profiler* prof = profiler_for_launch();
         if (prof) profiler_start(prof, a.stream);
-        KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.at(j), a.dt, beta_dev, a.ws,
-                              grad_dev + (j - 1), a.stream, false, 0.0, pe_reps),
+        KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, S.at(j), dt_b, beta_dev, a.ws,
+                              grad_dev + (j - 1), a.stream, acc, 0.0, pe_reps),
                "gradient bracket");
         if (prof) profiler_stop(prof, a.stream, kProfBracket, 2.0 * a.vb);
         if (first_order) {
@@ -358,10 +364,11 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
     }
   }
   if (centred) {
-    KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, a.psi0, a.dt, beta_dev, a.ws, &a.ws.st->g0,
-                          a.stream, false, 0.0, pe_reps),
+    KG_HIP(launch_bracket(a.prec, hc, a.geo.D, lam, a.psi0, dt_b, beta_dev, a.ws, &a.ws.st->g0,
+                          a.stream, acc, 0.0, pe_reps),
            "gradient bracket at t = 0");
-    KG_HIP(launch_centre(grad_dev, a.N, &a.ws.st->g0, a.stream), "centred gradient");
+    if (col == ncols - 1)
+      KG_HIP(launch_centre(grad_dev, a.N, &a.ws.st->g0, a.stream), "centred gradient");
   }
   return KG_OK;
 }
@@ -834,6 +841,91 @@ kg_status kg_profile_end(int64_t* launches, double* ms, double* bytes) {
   return st == KG_OK ? ok() : st;
 }
 
+// ---------------------------------------------------------------------- operator control
+
+namespace {
+
+// Forward sweeps of all columns (two per launch), the mean overlap, then one
+// costate sweep per column adding its brackets.
+kg_status columns_core(const kg_xxz* h, const Space& sp, const double* u_dev, int32_t N, double dt,
+                       const kg_krylov* k, int32_t prec, int32_t n_cols, const void* psi0s,
+                       const void* targets, double* F_dev, double* beta_dev, double* beta_cols_dev,
+                       double* grad_dev, void* states, int32_t ckpt_every, int32_t centred,
+                       void* ws, size_t ws_bytes, void* stream) {
+  if (n_cols < 1) return fail(KG_EINVAL, "n_cols=%d must be >= 1", n_cols);
+  if (!beta_dev || !beta_cols_dev || !grad_dev)
+    return fail(KG_EINVAL, "beta_dev, beta_cols_dev and grad_dev are required");
+  if ((uintptr_t)beta_cols_dev % 8) return fail(KG_EINVAL, "beta_cols_dev is not 8-byte aligned");
+  if (centred != 0 && centred != 1) return fail(KG_EINVAL, "centred must be 0 or 1");
+  Workspace W, W1;
+  KG_CHECK(carve_d(ws, ws_bytes, sp.geo.D, k, prec, &W, &W1));
+  const size_t vb = vbytes(sp.geo.D, prec);
+  const size_t sb = states_bytes_d(sp.geo.D, N, ckpt_every, prec);
+  const hipStream_t s = (hipStream_t)stream;
+  auto col_args = [&](int c, const Workspace& w0, const Workspace& w1) {
+    return SweepArgs{h, u_dev, N, dt, k, prec,
+                     static_cast<const char*>(psi0s) + (size_t)c * vb,
+                     static_cast<const char*>(targets) + (size_t)c * vb, sp.geo, w0, w1, s,
+                     sp.pe, vb};
+  };
+  auto col_states = [&](int c) {
+    return make_states(N, ckpt_every, static_cast<char*>(states) + (size_t)c * sb, vb,
+                       static_cast<const char*>(psi0s) + (size_t)c * vb);
+  };
+  KG_HIP(launch_init(W.st, s), "grape_gradient_columns");
+  KG_HIP(launch_init(W1.st, s), "grape_gradient_columns");
+  for (int c = 0; c < n_cols; c += 2) {
+    const SweepArgs a0 = col_args(c, W, W1);
+    const States S0 = col_states(c);
+    if (c + 1 < n_cols) {
+      const SweepArgs a1 = col_args(c + 1, W1, W);
+      const States S1 = col_states(c + 1);
+      for (int j = 1; j <= N; ++j) {
+        const KrylovCall k0 = krylov_call(a0, j, dt, S0.at0(j - 1), S0.at(j));
+        const KrylovCall k1 = krylov_call(a1, j, dt, S1.at0(j - 1), S1.at(j));
+        KG_HIP(launch_krylov_pair(k0, W, k1, W1, s), "column forward sweeps");
+      }
+      KG_HIP(launch_overlap(prec, sp.geo.D, a1.target, S1.at(N), W1, nullptr,
+                            beta_cols_dev + 2 * (c + 1), s),
+             "column overlap");
+    } else {
+      for (int j = 1; j <= N; ++j) {
+        const KrylovCall k0 = krylov_call(a0, j, dt, S0.at0(j - 1), S0.at(j));
+        KG_HIP(launch_krylov(k0, W, s), "column forward sweep");
+      }
+    }
+    KG_HIP(launch_overlap(prec, sp.geo.D, a0.target, S0.at(N), W, nullptr, beta_cols_dev + 2 * c,
+                          s),
+           "column overlap");
+  }
+  KG_HIP(launch_mean_overlap(beta_cols_dev, n_cols, beta_dev, F_dev, s), "mean overlap");
+  for (int c = 0; c < n_cols; ++c)
+    KG_CHECK(backward_sweep(col_args(c, W, W1), col_states(c), beta_dev, grad_dev, centred != 0,
+                            nullptr, false, c, n_cols));
+  return ok();
+}
+
+}  // namespace
+
+size_t kg_columns_states_bytes(const kg_xxz* h, int32_t n_cols, int32_t N, int32_t ckpt_every,
+                               int32_t prec) {
+  if (n_cols < 1) return 0;
+  const size_t one = kg_states_bytes(h, N, ckpt_every, prec);
+  return one * (size_t)n_cols;
+}
+
+kg_status grape_gradient_columns(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
+                                 const kg_krylov* k, int32_t prec, int32_t n_cols,
+                                 const void* psi0s, const void* targets, double* F_dev,
+                                 double* beta_dev, double* beta_cols_dev, double* grad_dev,
+                                 void* states, int32_t ckpt_every, int32_t centred, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0s, targets, states, ckpt_every));
+  const Space sp{make_geo(h->L, prec, tile_override_from_env()), nullptr};
+  return columns_core(h, sp, u_dev, N, dt, k, prec, n_cols, psi0s, targets, F_dev, beta_dev,
+                      beta_cols_dev, grad_dev, states, ckpt_every, centred, ws, ws_bytes, stream);
+}
+
 // ---------------------------------------------------------------------- reduced basis
 
 namespace {
@@ -1124,6 +1216,20 @@ kg_status grape_gradient_pe(const kg_xxz* h, const kg_pe* pe, const double* u_de
                        states, ckpt_every, states_valid, ws, ws_bytes, stream,
                        variant == KG_GRAD_CENTRED, "grape_gradient_pe", qp,
                        variant == KG_GRAD_FIRST_ORDER);
+}
+
+kg_status grape_gradient_columns_pe(const kg_xxz* h, const kg_pe* pe, const double* u_dev,
+                                    int32_t N, double dt, const kg_krylov* k, int32_t prec,
+                                    int32_t n_cols, const void* psi0s, const void* targets,
+                                    double* F_dev, double* beta_dev, double* beta_cols_dev,
+                                    double* grad_dev, void* states, int32_t ckpt_every,
+                                    int32_t centred, void* ws, size_t ws_bytes, void* stream) {
+  KG_CHECK(check_pe_chain(h, pe));
+  KG_CHECK(check_sweep(h, u_dev, N, dt, k, prec, psi0s, targets, states, ckpt_every, KG_PE_MAX_L));
+  const PeArgs pa = pe_args(pe);
+  const Space sp{make_geo_pe(h->L, (uint64_t)pe->dim), &pa};
+  return columns_core(h, sp, u_dev, N, dt, k, prec, n_cols, psi0s, targets, F_dev, beta_dev,
+                      beta_cols_dev, grad_dev, states, ckpt_every, centred, ws, ws_bytes, stream);
 }
 
 kg_status kg_debug_index_map(int32_t L, uint32_t s0, uint32_t count, int32_t* n_anti_dev,

@@ -130,6 +130,8 @@ hipError_t launch_hv_pe(int prec, const HvArgs& a, const PeArgs& p, const void* 
 hipError_t launch_init(KState* st, hipStream_t s);
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
 hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s);
+hipError_t launch_mean_overlap(const double* beta_cols, int n, double* beta, double* F,
+                               hipStream_t s);
 
 // batched persistent form (kg_batched.hip); kg_chain comes from kgrape.h
 }  // namespace kg

@@ -785,6 +785,21 @@ __global__ void __launch_bounds__(1024) k_centre(double* g, int N, const double*
   }
 }
 
+// beta = (1/n) sum_c beta_c (columns in order, one thread: deterministic), F = |beta|^2
+__global__ void k_mean_overlap(const double* beta_cols, int n, double* beta, double* F) {
+  if (threadIdx.x != 0) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < n; ++c) {
+    re += beta_cols[2 * c];
+    im += beta_cols[2 * c + 1];
+  }
+  re /= n;
+  im /= n;
+  beta[0] = re;
+  beta[1] = im;
+  if (F) *F = re * re + im * im;
+}
+
 __global__ void k_index_map(int L, uint32_t s0, uint32_t count, int32_t* n_anti, uint32_t* pmask) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -1030,6 +1045,12 @@ hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStrea
 
 hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s) {
   hipLaunchKernelGGL(k_centre, dim3(1), dim3(1024), 0, s, g, N, g0);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_overlap(const double* beta_cols, int n, double* beta, double* F,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_mean_overlap, dim3(1), dim3(64), 0, s, beta_cols, n, beta, F);
   return hipGetLastError();
 }
 

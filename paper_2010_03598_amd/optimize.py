@@ -153,33 +153,108 @@ def lbfgs(fg: FunGrad, x0, history: int = 10, max_iter: int = 200, f_target: flo
                        history=hist)
 
 
+class GradientEvaluator:
+    """One GPU gradient evaluation per call, u given on the host.
+
+    All buffers (controls, states, workspace, F, beta, gradient) are allocated
+    once.  With `graph`, the first call runs eagerly, the second records the
+    whole evaluation (every Krylov call, bracket and reduction: thousands of
+    launches) into one HIP graph on a side stream, and later calls copy u into
+    the static control buffer and replay the graph.  The kernels read u from
+    device memory, so the graph stays valid for any controls; nothing in the
+    evaluation records a memset.  `basis` (a ReducedBasis) runs the
+    evaluation in the fixed-excitation, even-parity basis."""
+
+    VARIANTS = ("zeroth", "centred", "first_order", "quadrature")
+
+    def __init__(self, h, N: int, dt: float, k, psi0, target, ckpt_every: int = 0,
+                 gradient: str = "centred", nodes: int = 4, basis=None, graph: bool = False):
+        import torch
+
+        from .api import Workspace, new_states
+        if gradient not in self.VARIANTS:
+            raise ValueError(f"gradient must be one of {self.VARIANTS}")
+        self.torch = torch
+        dev = psi0.device
+        self.N = int(N)
+        extended = gradient in ("first_order", "quadrature")
+        self.u = torch.zeros(self.N, dtype=torch.float64, device=dev)
+        self.F = torch.empty((), dtype=torch.float64, device=dev)
+        self.beta = torch.empty(2, dtype=torch.float64, device=dev)
+        self.grad = torch.empty(self.N, dtype=torch.float64, device=dev)
+        if basis is None:
+            from . import api
+            ws = Workspace(h, k, psi0.dtype, dev, extended=extended)
+            states = new_states(h, self.N, ckpt_every, psi0.dtype, dev)
+            opts = {"zeroth": {}, "centred": {"centred": True},
+                    "first_order": {"first_order": True}, "quadrature": {"nodes": nodes}}[gradient]
+
+            def run():
+                api.grape_gradient(h, self.u, dt, k, psi0, target, ckpt_every=ckpt_every,
+                                   states=states, workspace=ws, F=self.F, beta=self.beta,
+                                   grad=self.grad, **opts)
+        else:
+            from . import reduced
+            ws = reduced.ReducedWorkspace(basis, k, psi0.dtype, dev, extended=extended)
+            states = reduced.pe_states(basis, self.N, ckpt_every, psi0.dtype, dev)
+
+            def run():
+                reduced.grape_gradient_pe(h, basis, self.u, dt, k, psi0, target,
+                                          ckpt_every=ckpt_every, variant=gradient,
+                                          nodes=nodes if gradient == "quadrature" else 0,
+                                          states=states, workspace=ws, F=self.F,
+                                          beta=self.beta, grad=self.grad)
+        self._keep = (ws, states)
+        self._run = run
+        self.graph = graph
+        self._g = None
+        self.calls = 0
+
+    def _capture(self):
+        torch = self.torch
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                self._run()
+        torch.cuda.current_stream().wait_stream(s)
+        self._g = g
+
+    def __call__(self, u):
+        torch = self.torch
+        self.u.copy_(torch.from_numpy(np.ascontiguousarray(u, dtype=np.float64)))
+        if self.graph and self.calls >= 1:
+            if self._g is None:
+                self._capture()
+            self._g.replay()
+        else:
+            self._run()
+        self.calls += 1
+        torch.cuda.synchronize()
+        return float(self.F.cpu()), self.grad.cpu().numpy().copy()
+
+
 def optimize_controls(h, u0, dt: float, k, psi0, target, ckpt_every: int = 0,
                       gradient: str = "centred", I_target: float = 1e-2, max_iter: int = 200,
-                      history: int = 10, nodes: int = 4, callback=None) -> LbfgsResult:
+                      history: int = 10, nodes: int = 4, callback=None, basis=None,
+                      graph: bool = False) -> LbfgsResult:
     """Minimise the infidelity I(u) = 1 - F(u) over the controls with L-BFGS,
     every evaluation one GPU gradient (`gradient`: "zeroth", "centred",
     "first_order" or "quadrature" with `nodes` Gauss-Legendre nodes).  Stops at
-    I <= I_target or when I changes by less than ten machine epsilons."""
-    import torch
-
-    from .api import Workspace, grape_gradient, new_states
-
-    dev = psi0.device
-    N = int(np.asarray(u0).size)
-    ws = Workspace(h, k, psi0.dtype, dev, extended=gradient in ("first_order", "quadrature"))
-    states = new_states(h, N, ckpt_every, psi0.dtype, dev)
-    u_dev = torch.empty(N, dtype=torch.float64, device=dev)
-    opts = {"zeroth": {}, "centred": {"centred": True}, "first_order": {"first_order": True},
-            "quadrature": {"nodes": nodes}}[gradient]
+    I <= I_target or when I changes by less than ten machine epsilons.
+    `basis` runs in a ReducedBasis (vectors of its dimension); `graph` replays
+    each evaluation from a captured HIP graph."""
+    ev = GradientEvaluator(h, int(np.asarray(u0).size), dt, k, psi0, target, ckpt_every,
+                           gradient, nodes, basis, graph)
 
     def fg(u):
-        u_dev.copy_(torch.from_numpy(np.ascontiguousarray(u)))
-        r = grape_gradient(h, u_dev, dt, k, psi0, target, ckpt_every=ckpt_every, states=states,
-                           workspace=ws, **opts)
-        return 1.0 - float(r.F.cpu()), -r.grad.cpu().numpy()
+        F, g = ev(u)
+        return 1.0 - F, -g
 
-    return lbfgs(fg, np.asarray(u0, dtype=np.float64), history=history, max_iter=max_iter,
-                 f_target=I_target, callback=callback)
+    res = lbfgs(fg, np.asarray(u0, dtype=np.float64), history=history, max_iter=max_iter,
+                f_target=I_target, callback=callback)
+    return res
 
 
-__all__ = ["lbfgs", "optimize_controls", "LbfgsResult"]
+__all__ = ["lbfgs", "optimize_controls", "LbfgsResult", "GradientEvaluator"]

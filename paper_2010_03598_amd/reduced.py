@@ -156,7 +156,9 @@ def grape_gradient_pe(h: XXZ, B: ReducedBasis, u: torch.Tensor, dt: float, k: Kr
                       variant: str = "zeroth", nodes: int = 0,
                       states: Optional[torch.Tensor] = None, states_valid: bool = False,
                       beta: Optional[torch.Tensor] = None,
-                      workspace: Optional[ReducedWorkspace] = None) -> GrapeResult:
+                      workspace: Optional[ReducedWorkspace] = None,
+                      F: Optional[torch.Tensor] = None,
+                      grad: Optional[torch.Tensor] = None) -> GrapeResult:
     """Fidelity and gradient in the reduced basis; `variant` is "zeroth",
     "centred", "first_order" or "quadrature" (with `nodes`)."""
     dtype = psi0.dtype
@@ -173,10 +175,13 @@ def grape_gradient_pe(h: XXZ, B: ReducedBasis, u: torch.Tensor, dt: float, k: Kr
         raise ValueError("states_valid needs beta from grape_forward_pe")
     v = _VARIANTS[variant]
     ws = _rws(workspace, B, k, dtype, dev, extended=v in (KG_GRAD_FIRST_ORDER, KG_GRAD_QUADRATURE))
-    F = torch.empty((), dtype=torch.float64, device=dev)
+    if F is None:
+        F = torch.empty((), dtype=torch.float64, device=dev)
     if beta is None:
         beta = torch.empty(2, dtype=torch.float64, device=dev)
-    grad = torch.empty(N, dtype=torch.float64, device=dev)
+    if grad is None:
+        grad = torch.empty(N, dtype=torch.float64, device=dev)
+    _f64(grad, N, "grad")
     _lib.check("grape_gradient_pe", _lib.load().grape_gradient_pe(
         ctypes.byref(h.c()), B.ref(), _ptr(u), N, float(dt), ctypes.byref(k.c()), prec_of(dtype),
         _ptr(psi0), _ptr(target), _ptr(F), _ptr(beta), _ptr(grad), _ptr(states), int(ckpt_every),
