@@ -86,6 +86,7 @@ def time_gradients(kg, torch, c, dtype, ckpt, steps, warmup, profile_every=0):
 def time_hv(kg, torch, L, dtype, reps=50):
     """Device time per H v launch: `reps` launches captured in one HIP graph and
     replayed between two events, so host-side call overhead does not enter."""
+    from paper_2010_03598_amd._graph import capture_guard
     h = kg.XXZ(L, 1.0, 0.5)
     D = 1 << L
     g = torch.Generator(device="cuda")
@@ -100,7 +101,7 @@ def time_hv(kg, torch, L, dtype, reps=50):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
+    with capture_guard(), torch.cuda.graph(graph):
         for _ in range(reps):
             kg.xxz_apply(h, 0.3, v, out=w)
     graph.replay()
@@ -126,6 +127,7 @@ def time_pe(kg, torch, workloads, steps=2, reps=20):
     evaluations with sampled kernel timing, one FP64 evaluation for the error,
     and the gather H v alone in a HIP graph."""
     import numpy as np
+    from paper_2010_03598_amd._graph import capture_guard
     t = workloads.pe_large()
     B = kg.ReducedBasis(t.L, t.K)
     tab = kg.pe_tables_host(t.L, t.K)
@@ -181,7 +183,7 @@ def time_pe(kg, torch, workloads, steps=2, reps=20):
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
+    with capture_guard(), torch.cuda.graph(graph):
         for _ in range(reps):
             kg.xxz_pe_apply(h, B, 0.3, x, out=y)
     graph.replay()

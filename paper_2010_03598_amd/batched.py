@@ -180,8 +180,9 @@ class CapturedStep:
             batch.ascent_step(eta)           # warm-up outside the capture
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
+        from ._graph import capture_guard
         self.graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(self.graph):
+        with capture_guard(), torch.cuda.graph(self.graph):
             batch.ascent_step(eta)
 
     def replay(self) -> None:

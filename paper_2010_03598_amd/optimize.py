@@ -178,10 +178,12 @@ class GradientEvaluator:
         dev = psi0.device
         self.N = int(N)
         extended = gradient in ("first_order", "quadrature")
-        self.u = torch.zeros(self.N, dtype=torch.float64, device=dev)
-        self.F = torch.empty((), dtype=torch.float64, device=dev)
-        self.beta = torch.empty(2, dtype=torch.float64, device=dev)
-        self.grad = torch.empty(self.N, dtype=torch.float64, device=dev)
+        # the closure below holds these buffers, not the evaluator, so that a
+        # dropped evaluator is freed at once rather than by the cycle collector
+        u = self.u = torch.zeros(self.N, dtype=torch.float64, device=dev)
+        F = self.F = torch.empty((), dtype=torch.float64, device=dev)
+        beta = self.beta = torch.empty(2, dtype=torch.float64, device=dev)
+        grad = self.grad = torch.empty(self.N, dtype=torch.float64, device=dev)
         if basis is None:
             from . import api
             ws = Workspace(h, k, psi0.dtype, dev, extended=extended)
@@ -190,20 +192,20 @@ class GradientEvaluator:
                     "first_order": {"first_order": True}, "quadrature": {"nodes": nodes}}[gradient]
 
             def run():
-                api.grape_gradient(h, self.u, dt, k, psi0, target, ckpt_every=ckpt_every,
-                                   states=states, workspace=ws, F=self.F, beta=self.beta,
-                                   grad=self.grad, **opts)
+                api.grape_gradient(h, u, dt, k, psi0, target, ckpt_every=ckpt_every,
+                                   states=states, workspace=ws, F=F, beta=beta, grad=grad,
+                                   **opts)
         else:
             from . import reduced
             ws = reduced.ReducedWorkspace(basis, k, psi0.dtype, dev, extended=extended)
             states = reduced.pe_states(basis, self.N, ckpt_every, psi0.dtype, dev)
 
             def run():
-                reduced.grape_gradient_pe(h, basis, self.u, dt, k, psi0, target,
+                reduced.grape_gradient_pe(h, basis, u, dt, k, psi0, target,
                                           ckpt_every=ckpt_every, variant=gradient,
                                           nodes=nodes if gradient == "quadrature" else 0,
-                                          states=states, workspace=ws, F=self.F,
-                                          beta=self.beta, grad=self.grad)
+                                          states=states, workspace=ws, F=F, beta=beta,
+                                          grad=grad)
         self._keep = (ws, states)
         self._run = run
         self.graph = graph
@@ -211,11 +213,12 @@ class GradientEvaluator:
         self.calls = 0
 
     def _capture(self):
+        from ._graph import capture_guard
         torch = self.torch
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         g = torch.cuda.CUDAGraph()
-        with torch.cuda.stream(s):
+        with capture_guard(), torch.cuda.stream(s):
             with torch.cuda.graph(g, stream=s):
                 self._run()
         torch.cuda.current_stream().wait_stream(s)

@@ -1,10 +1,12 @@
 """The host L-BFGS driver on objectives with known minima (no GPU)."""
 
+import os
+
 import numpy as np
 import pytest
 import scipy.optimize as so
 
-from paper_2010_03598_amd import optimize
+from paper_2010_03598_amd import _lib, optimize
 
 
 def rosen(x):
@@ -52,3 +54,29 @@ def test_stops_at_target_and_on_stagnation():
     assert r.reason == "f_target" and r.f <= 1e-3
     r = optimize.lbfgs(lambda x: (1.0, np.zeros_like(x)), np.ones(3), g_tol=-1.0)
     assert r.reason in ("line_search", "df_min")
+
+
+@pytest.mark.skipif(not os.path.exists(_lib.LIB_PATH), reason="libkgrape.so not built")
+def test_evaluator_is_freed_without_the_cycle_collector():
+    """A dropped GradientEvaluator releases its buffers (and any captured graph) by
+    reference counting alone: a collection by the cycle collector could otherwise
+    free device memory in the middle of a later graph capture.  (The buffers are
+    host tensors here; nothing runs.)"""
+    import gc
+    import weakref
+
+    import torch
+
+    import paper_2010_03598_amd as kg
+    psi0 = torch.zeros(64, dtype=torch.complex128)
+    ev = optimize.GradientEvaluator(kg.XXZ(6), 5, 0.1, kg.Krylov(8), psi0, psi0, ckpt_every=2,
+                                    gradient="centred", graph=True)
+    ref = weakref.ref(ev)
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        del ev
+        assert ref() is None
+    finally:
+        if was:
+            gc.enable()
