@@ -198,3 +198,65 @@ def test_full_size_mixed_vs_fp64():
     assert F128 > 0.0
     assert abs(F64 - F128) <= 1e-4 * F128
     assert rel_err(g64, g128) <= 1e-4
+
+
+class BruteBasis:
+    """The orbit basis of a small sector of a long chain, from combinations of
+    zero positions (the oracle's PEBasis enumerates all 2^L states, too many at
+    L = 32); same attributes as PEBasis for the oracle's reduced H v."""
+
+    def __init__(self, L, K):
+        from itertools import combinations
+        full = (1 << L) - 1
+        states = sorted(full & ~sum(1 << z for z in zs) for zs in combinations(range(L), K))
+        rev = lambda s: int(format(s, f"0{L}b")[::-1], 2)
+        self.L, self.K = L, K
+        self.reps = np.array([s for s in states if s <= rev(s)], dtype=np.int64)
+        self.n = np.array([1 if rev(int(r)) == int(r) else 2 for r in self.reps])
+        self.dim = self.reps.size
+        self._pos = {int(r): i for i, r in enumerate(self.reps)}
+        self._rev = rev
+
+    def index(self, s):
+        s = np.asarray(s, dtype=np.int64)
+        return np.array([self._pos[min(int(v), self._rev(int(v)))] for v in s.ravel()],
+                        dtype=np.int64).reshape(s.shape)
+
+
+@pytest.mark.parametrize("L,K", [(32, 2), (31, 3), (32, 1)])
+def test_apply_at_the_largest_chains(L, K):
+    Bo = BruteBasis(L, K)
+    sites = 1 | (1 << (L - 1))
+    x = rand_vec(L + K, Bo.dim)
+    ref = pe.apply_h_pe(Bo, 2.0, 0.5, sites, -0.4, x)
+    B = kg.ReducedBasis(L, K)
+    assert B.dim == Bo.dim
+    y = host(kg.xxz_pe_apply(kg.XXZ(L, 2.0, 0.5, _lib.KG_HC_SZ, sites), B, -0.4, dev_vec(x)))
+    assert np.abs(y - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_gradient_at_L32():
+    """Zeroth-order gradient of a random transfer in the (32, 2) sector vs the oracle's
+    sweeps on the reduced chain."""
+    L, K, N, dt, m = 32, 2, 12, 0.3, 12
+    Bo = BruteBasis(L, K)
+    sites = 1 | (1 << (L - 1))
+
+    class Chain:
+        def apply(self, u, v):
+            return pe.apply_h_pe(Bo, 2.0, 0.5, sites, u, v)
+
+        def apply_hc(self, v):
+            from oracle import model
+            return model.sz_control_diag(L, sites, Bo.reps).real * v
+
+    rng = np.random.default_rng(4)
+    u = rng.uniform(-1, 1, N)
+    x0, x1 = rand_vec(5, Bo.dim), rand_vec(6, Bo.dim)
+    ref = grape.gradient(Chain(), u, x0, x1, dt, m, True, krylov.default_tol())
+    B = kg.ReducedBasis(L, K)
+    r = kg.grape_gradient_pe(kg.XXZ(L, 2.0, 0.5, _lib.KG_HC_SZ, sites), B,
+                             torch.tensor(u, device="cuda"), dt, kg.Krylov(m), dev_vec(x0),
+                             dev_vec(x1), ckpt_every=4)
+    assert abs(float(host(r.F)) - ref.F) <= 1e-10 * ref.F
+    assert rel_err(host(r.grad), ref.grad) <= 1e-10

@@ -124,3 +124,42 @@ def test_gradient_variant_checked():
     assert "nodes" in _lib.last_error()
     assert lib.grape_gradient_pe(*args, _lib.KG_GRAD_QUADRATURE, 0, v, 1 << 20, None) == _lib.KG_EINVAL
     assert "nodes" in _lib.last_error()
+
+
+def brute_sector_orbits(L, K):
+    """Orbit labels of the K-zero patterns of L bits, from combinations of zero
+    positions (no enumeration of 2^L states)."""
+    from itertools import combinations
+    full = (1 << L) - 1
+    rev = lambda s: int(format(s, f"0{L}b")[::-1], 2)
+    states = sorted(full & ~sum(1 << z for z in zs) for zs in combinations(range(L), K))
+    return [s for s in states if s <= rev(s)], states
+
+
+@pytest.mark.parametrize("L,K", [(32, 1), (32, 2), (31, 2), (32, 31), (32, 32), (32, 0)])
+def test_tables_at_the_largest_chains(L, K):
+    reps, states = brute_sector_orbits(L, K)
+    t = tables(L, K)
+    assert list(t["reps"].astype(np.int64)) == reps
+    ranks = [combinatorial_rank(s, L) for s in states]
+    assert sorted(ranks) == list(range(comb(L, K)))
+    pos = {r: i for i, r in enumerate(reps)}
+    rev = lambda s: int(format(s, f"0{L}b")[::-1], 2)
+    for s, rk in zip(states, ranks):
+        assert t["index"][rk] == pos[min(s, rev(s))]
+
+
+def test_columns_validation():
+    lib = _lib.load()
+    h = _lib.KgXxz(8, _lib.KG_HC_SX, 1.0, 0.5, 1)
+    k = _lib.KgKrylov(10, 1, 0.0)
+    v = ctypes.c_void_p(1 << 20)
+    base = [ctypes.byref(h), v, 4, 0.1, ctypes.byref(k), _lib.KG_C128]
+    tail = [v, v, v, v, v, v, v, 0]
+    assert lib.grape_gradient_columns(*base, 0, *tail, 0, v, 1 << 20, None) == _lib.KG_EINVAL
+    assert "n_cols" in _lib.last_error()
+    assert lib.grape_gradient_columns(*base, 2, *tail, 2, v, 1 << 20, None) == _lib.KG_EINVAL
+    assert "centred" in _lib.last_error()
+    assert lib.kg_columns_states_bytes(ctypes.byref(h), 3, 10, 0, _lib.KG_C64) == \
+        3 * lib.kg_states_bytes(ctypes.byref(h), 10, 0, _lib.KG_C64)
+    assert lib.kg_columns_states_bytes(ctypes.byref(h), 0, 10, 0, _lib.KG_C64) == 0
