@@ -302,7 +302,7 @@ def time_batched(kg, torch, workloads, steps=3, fp64=True):
     return out
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pass_a_L20_c64_traffic.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lanczos_L20_c64_traffic.md")
 KERNEL_OF_CLASS = {"pass_a": "k_pass_a", "pass_b": "k_pass_b", "combine": "k_combine"}
 
 

@@ -113,9 +113,9 @@ int32_t kg_version(void);
 
 /* Bytes of workspace that krylov_expv, grape_forward and grape_gradient need
  * for this chain, Krylov dimension and precision: two Krylov slots (scalars,
- * reduction partials, m-1 basis vectors and one H v vector each; the second
- * slot advances the segment recomputation beside the backward sweep) and one
- * costate vector.
+ * reduction partials, m-1 basis vectors and the m vectors H v_i each; the
+ * second slot advances the segment recomputation beside the backward sweep)
+ * and one costate vector.
  * Returns 0 for invalid arguments. */
 size_t kg_workspace_bytes(const kg_xxz* h, const kg_krylov* k, int32_t prec);
 

@@ -131,9 +131,11 @@ HvArgs make_hv(const kg_xxz* h, const double* u_ptr, double u_val) {
 
 size_t vbytes(uint64_t D, int32_t prec) { return (size_t)D * (prec == KG_C128 ? 16 : 8); }
 
+// A Krylov slot: scalars, reduction partials, basis vectors 1..m-1 and the
+// m vectors y_i = H v_i.
 size_t slot_bytes_d(uint64_t D, const kg_krylov* k, int32_t prec) {
   return ws_fixed_bytes() + align_up(vbytes(D, prec) * (size_t)(k->m - 1), 256) +
-         align_up(vbytes(D, prec), 256);
+         align_up(vbytes(D, prec) * (size_t)k->m, 256);
 }
 
 // workspace of vectors of D amplitudes; `extended` adds the two node vectors
@@ -174,7 +176,7 @@ kg_status carve_d(void* ws, size_t ws_bytes, uint64_t D, const kg_krylov* k, int
     q += align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
     o->basis = q;
     q += align_up(vbytes(D, prec) * (size_t)(k->m - 1), 256);
-    o->hx = q;
+    o->ywin = q;
     o->lam = p + 2 * slot_bytes_d(D, k, prec);
     o->node_a = extended ? static_cast<char*>(o->lam) + vb : nullptr;
     o->node_b = extended ? static_cast<char*>(o->lam) + 2 * vb : nullptr;

@@ -211,6 +211,9 @@ constexpr uint32_t kGroup = 64;        // blocks per group of the two-level redu
 // do not depend on which block arrives last.  When `xrows` is given (one
 // value per block in column 0, row stride kMaxScal, written by an earlier
 // kernel) its sum over the G blocks lands in tot[ns] by the same scheme.
+// With c0 > 0 this launch formed only columns [c0, ns): each block writes
+// those, and columns [0, c0) of the same rows were written by an earlier
+// kernel; the sums cover all columns.
 //
 // The partials travel only through device-scope (sc1) stores and loads, which
 // are coherent across the XCDs' L2 caches; the stores are waited for before
@@ -218,15 +221,17 @@ constexpr uint32_t kGroup = 64;        // blocks per group of the two-level redu
 // L2 caches are never written back or invalidated here.  counters[0] counts
 // the top level, counters[1 + g] group g.
 __device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* counters, uint32_t b,
-                            uint32_t G, const cplx_d* xrows = nullptr) {
+                            uint32_t G, const cplx_d* xrows = nullptr, int c0 = 0) {
   const int lane = threadIdx.x & 63;
   if (G == 1) {
+    for (int j = threadIdx.x; j < c0; j += blockDim.x)
+      tot[j] = cplx_d{ld_agent(&partials[j].re), ld_agent(&partials[j].im)};
     if (xrows && threadIdx.x == 0) tot[ns] = cplx_d{ld_agent(&xrows[0].re), ld_agent(&xrows[0].im)};
     __syncthreads();
     return true;
   }
   if ((threadIdx.x >> 6) == 0) {
-    for (int j = lane; j < ns; j += 64) {
+    for (int j = c0 + lane; j < ns; j += 64) {
       st_agent(&partials[(size_t)b * kMaxScal + j].re, tot[j].re);
       st_agent(&partials[(size_t)b * kMaxScal + j].im, tot[j].im);
     }
@@ -257,11 +262,11 @@ __device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* cou
   return true;
 }
 
-// Sum the per-wavefront accumulators wacc[w * kMaxScal + j] of a block in
-// wavefront order.
-__device__ void block_totals(const cplx_d* wacc, int ns, cplx_d* tot) {
+// Sum the per-wavefront accumulators wacc[w * kMaxScal + j], j in [c0, ns), of
+// a block in wavefront order.
+__device__ void block_totals(const cplx_d* wacc, int ns, cplx_d* tot, int c0 = 0) {
   const int nw = blockDim.x >> 6;
-  for (int j = threadIdx.x; j < ns; j += blockDim.x) {
+  for (int j = c0 + (int)threadIdx.x; j < ns; j += blockDim.x) {
     double re = 0.0, im = 0.0;
     for (int q = 0; q < nw; ++q) {
       re += wacc[q * kMaxScal + j].re;

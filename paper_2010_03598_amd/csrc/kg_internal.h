@@ -68,7 +68,7 @@ struct Workspace {         // carved from the caller's workspace
   KState* st;
   cplx_d* partials;        // [kPartialRows][kMaxScal]
   void* basis;             // m-1 vectors (stored Krylov vectors 1..m-1)
-  void* hx;                // one vector: H v_k of the running basis step
+  void* ywin;              // m vectors: y_i = H v_i of the running basis
   void* lam;               // one vector (costate)
   void* node_a;            // quadrature workspaces only: psi at a node
   void* node_b;            //   and lambda at the node

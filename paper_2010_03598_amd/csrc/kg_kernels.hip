@@ -181,11 +181,11 @@ struct LzArgs {
   Geo geo;
   const void* slot0;  // stored vector 0: the input of the Krylov call
   void* basis;        // stored vectors 1..m-1
-  void* hx;           // y = H v_k, written by pass A, read by pass B
+  void* ywin;         // y_i = H v_i, i = 0..m-1 (y_k written by pass A(k))
   int32_t k;          // basis step
   int32_t i0;         // first index of the projection window [i0, k]
   int32_t m;
-  int32_t pad_;
+  int32_t i0n;        // pass B(k): first index of the next step's window
   double t;
   double tol;
   KState* st;
@@ -209,6 +209,11 @@ template <typename V>
 __device__ __forceinline__ const V* slot_ptr(const LzArgs& a, int i) {
   return i == 0 ? reinterpret_cast<const V*>(a.slot0)
                 : reinterpret_cast<const V*>(a.basis) + (size_t)(i - 1) * a.geo.D;
+}
+
+template <typename V>
+__device__ __forceinline__ V* y_ptr(const LzArgs& a, int i) {
+  return reinterpret_cast<V*>(a.ywin) + (size_t)i * a.geo.D;
 }
 
 // Scalar tail of a basis: exp(-itT) e_1 on wavefront 0 of the finishing block
@@ -239,8 +244,30 @@ __device__ void finish_basis(const LzArgs& a, int m_eff, double fresh_alpha, dou
   }
 }
 
-// kYIn: y = H v_k was written to a.hx by a separate H v kernel (the reduced
-// basis); the pass then streams x and y instead of forming y on the tile.
+template <typename R, int RB>
+__device__ __forceinline__ void store_y(const Tile<R, RB>& T, typename VT<R>::T* yk, uint32_t base,
+                                        uint32_t eb, const Geo& g) {
+  using V = typename VT<R>::T;
+#pragma unroll
+  for (int r = 0; r < (1 << RB); ++r) {
+    const uint32_t s = base | eb | ((uint32_t)r << 6);
+    if (!g.small || s < g.D) {
+      V o;
+      o.x = T.yr[r];
+      o.y = T.yi[r];
+      yk[s] = o;
+    }
+  }
+}
+
+// Pass A(k): y = H v_k, stored as y_k (the last step keeps it in registers),
+// and this block's parts of <v_k|y> and ||v_k||^2 (window columns nwin-1 and
+// nwin).  The window dots <v_i|y> for i in [i0, k) need no window reads here:
+// pass B(k-1) formed them as <y_i|w> (H is Hermitian and v_k = w) in columns
+// 0..nwin-2 of the same partials rows.  The finishing block adds the columns
+// of both passes and pass B's norm parts, then runs the scalar update.
+// kYIn: y_k was written by a separate H v kernel (the reduced basis); the pass
+// then loads it instead of forming it on the tile.
 template <typename R, int RB, bool kYIn = false>
 __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
@@ -254,11 +281,11 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
   const uint32_t eb = lane | (wv << (6 + RB));
-  // lane l accumulates window entry l across the tiles of this block
-  double acc_re = 0.0, acc_im = 0.0, acc_nn = 0.0;
+  double acc_re = 0.0, acc_im = 0.0, acc_nn = 0.0;   // this wavefront's totals
 
   const double u = control_value(a.hv);
   const V* x = slot_ptr<V>(a, a.k);
+  V* yk = y_ptr<V>(a, a.k);
   const uint32_t iters = a.geo.ntiles / G;
   Tile<R, RB> T;
   for (uint32_t it = 0; it < iters; ++it) {
@@ -266,13 +293,12 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     if (it) __syncthreads();
     const uint32_t base = tile << a.geo.TB;
     if constexpr (kYIn) {
-      const V* yv = reinterpret_cast<const V*>(a.hx);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const uint32_t s = base | eb | ((uint32_t)r << 6);
         const bool ok = s < a.geo.D;
         const V xv = ok ? x[s] : V{(R)0, (R)0};
-        const V yy = ok ? yv[s] : V{(R)0, (R)0};
+        const V yy = ok ? yk[s] : V{(R)0, (R)0};
         T.xr[r] = xv.x;
         T.xi[r] = xv.y;
         T.yr[r] = yy.x;
@@ -282,90 +308,33 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     } else {
       if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, a.k > 0 ? &a.st->done : nullptr))
         return;
+      // y_k for pass B and for the window dots of later steps
+      if (a.k + 1 < a.m) store_y<R, RB>(T, yk, base, eb, a.geo);
     }
-    if (!kYIn && a.k + 1 < a.m) {
-      // y for pass B (the last step has no pass B)
-      V* yv = reinterpret_cast<V*>(a.hx);
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const uint32_t s = base | eb | ((uint32_t)r << 6);
-        if (!a.geo.small || s < a.geo.D) {
-          V o;
-          o.x = T.yr[r];
-          o.y = T.yi[r];
-          yv[s] = o;
-        }
-      }
-    }
-    // window vectors other than v_k, NW per round trip
-    constexpr int NW = WinSlots<R, RB>::n;
-    for (int i = a.i0; i < a.k; i += NW) {
-      V q[NW][NR];
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        if (i + j < a.k) {
-          const V* vj = slot_ptr<V>(a, i + j);
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const uint32_t s = base | eb | ((uint32_t)r << 6);
-            const bool ok = !a.geo.small || s < a.geo.D;
-            q[j][r] = ok ? vj[s] : V{(R)0, (R)0};
-          }
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        if (i + j < a.k) {
-          double sr = 0.0, si = 0.0;
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const double yr = T.yr[r], yi = T.yi[r];
-            const double vr = q[j][r].x, vi = q[j][r].y;
-            sr += vr * yr + vi * yi;
-            si += vr * yi - vi * yr;
-          }
-          sr = wave_sum(sr);
-          si = wave_sum(si);
-          if ((int)lane == i + j - a.i0) {
-            acc_re += sr;
-            acc_im += si;
-          }
-        }
-      }
-    }
-    {
-      // v_k itself, from registers
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const double vr = T.xr[r], vi = T.xi[r], yr = T.yr[r], yi = T.yi[r];
-        sr += vr * yr + vi * yi;
-        si += vr * yi - vi * yr;
-      }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
-      if ((int)lane == a.k - a.i0) {
-        acc_re += sr;
-        acc_im += si;
-      }
-    }
-    double nn = 0.0;
+    // <v_k|y> and ||v_k||^2 from registers
+    double sr = 0.0, si = 0.0, nn = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const double vr = T.xr[r], vi = T.xi[r];
+      const double vr = T.xr[r], vi = T.xi[r], yr = T.yr[r], yi = T.yi[r];
+      sr += vr * yr + vi * yi;
+      si += vr * yi - vi * yr;
       nn += vr * vr + vi * vi;
     }
+    acc_re += wave_sum(sr);
+    acc_im += wave_sum(si);
     acc_nn += wave_sum(nn);
   }
   __syncthreads();
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
-  if ((int)lane < nwin) wacc[wv * kMaxScal + lane] = cplx_d{acc_re, acc_im};
-  if (lane == 0) wacc[wv * kMaxScal + nwin] = cplx_d{acc_nn, 0.0};
+  if (lane == 0) {
+    wacc[wv * kMaxScal + nwin - 1] = cplx_d{acc_re, acc_im};
+    wacc[wv * kMaxScal + nwin] = cplx_d{acc_nn, 0.0};
+  }
   __syncthreads();
-  block_totals(wacc, ns, tot);
-  // for k >= 1 the norm parts of pass B(k-1) are summed into tot[ns]
+  block_totals(wacc, ns, tot, nwin - 1);
+  // columns [0, nwin-1) come from pass B(k-1); for k >= 1 its norm parts land in tot[ns]
   if (!grid_reduce(tot, ns, a.partials, a.st->counters, bl, G,
-                   a.k > 0 ? a.partials + kNormCol : nullptr))
+                   a.k > 0 ? a.partials + kNormCol : nullptr, nwin - 1))
     return;
   if (threadIdx.x >= 64) return;
 
@@ -447,6 +416,10 @@ __global__ void __launch_bounds__(1024) k_pass_a_y(LzBatch B) {
   }
 }
 
+// Pass B(k): w = s_k y_k - sum_i c_i v_i over the window [i0, k] (FP64), stored
+// unnormalised as v_{k+1}, with this block's part of ||w||^2 (column kNormCol)
+// and of the next step's window dots <v_i|H w> = <y_i|w>, i in [i0n, k]
+// (columns 0..k-i0n), against the stored H v vectors and the stored w.
 template <typename R, int RB>
 __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
@@ -458,11 +431,13 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
   const uint32_t eb = lane | (wv << (6 + RB));
+  const int nd = a.k - a.i0n + 1;   // next step's dots formed here (0 before the last step)
   double acc_nn = 0.0;
+  double acc_re = 0.0, acc_im = 0.0;   // lane l: dot of column l
 
   const KState* st = a.st;
   const V* x = slot_ptr<V>(a, a.k);
-  const V* yv = reinterpret_cast<const V*>(a.hx);
+  const V* yv = y_ptr<V>(a, a.k);
   V* out = reinterpret_cast<V*>(a.basis) + (size_t)a.k * a.geo.D;
   const uint32_t iters = a.geo.ntiles / G;
   // same block-to-tile map as pass A, so y is read back from the L2 that wrote it
@@ -517,6 +492,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
         }
       }
     }
+    // store w; the dots below use the stored (rounded) values
     double nn = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -524,20 +500,66 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
       V o;
       o.x = (R)zr[r];
       o.y = (R)zi[r];
+      zr[r] = o.x;
+      zi[r] = o.y;
       if (!a.geo.small || s < a.geo.D) {
         out[s] = o;
-        nn += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+        nn += zr[r] * zr[r] + zi[r] * zi[r];
+      } else {
+        zr[r] = zi[r] = 0.0;
       }
     }
     acc_nn += wave_sum(nn);
+    // next step's window dots <y_i|w>, NW per round trip; y_k is in registers
+    for (int i = a.i0n; i <= a.k; i += NW) {
+      V q[NW][NR];
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        if (i + j < a.k) {
+          const V* yj = y_ptr<V>(a, i + j);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const uint32_t s = base | eb | ((uint32_t)r << 6);
+            const bool ok = !a.geo.small || s < a.geo.D;
+            q[j][r] = ok ? yj[s] : V{(R)0, (R)0};
+          }
+        } else if (i + j == a.k) {
+#pragma unroll
+          for (int r = 0; r < NR; ++r) q[j][r] = yo[r];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < NW; ++j) {
+        if (i + j <= a.k) {
+          double sr = 0.0, si = 0.0;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double yr = q[j][r].x, yi = q[j][r].y;
+            sr += yr * zr[r] + yi * zi[r];
+            si += yr * zi[r] - yi * zr[r];
+          }
+          sr = wave_sum(sr);
+          si = wave_sum(si);
+          if ((int)lane == i + j - a.i0n) {
+            acc_re += sr;
+            acc_im += si;
+          }
+        }
+      }
+    }
   }
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
-  if (lane == 0) wacc[wv * kMaxScal] = cplx_d{acc_nn, 0.0};
+  if ((int)lane < nd) wacc[wv * kMaxScal + lane] = cplx_d{acc_re, acc_im};
+  if (lane == 0) wacc[wv * kMaxScal + nd] = cplx_d{acc_nn, 0.0};
   __syncthreads();
-  block_totals(wacc, 1, tot);
-  // this block's part of ||w||^2, summed by the finishing block of pass A(k+1)
+  block_totals(wacc, nd + 1, tot);
+  // this block's row: the next step's dots, and its part of ||w||^2 for pass A(k+1)
+  for (int j = threadIdx.x; j < nd; j += blockDim.x) {
+    st_agent(&a.partials[(size_t)bl * kMaxScal + j].re, tot[j].re);
+    st_agent(&a.partials[(size_t)bl * kMaxScal + j].im, tot[j].im);
+  }
   if (threadIdx.x == 0) {
-    st_agent(&a.partials[(size_t)bl * kMaxScal + kNormCol].re, tot[0].re);
+    st_agent(&a.partials[(size_t)bl * kMaxScal + kNormCol].re, tot[nd].re);
     st_agent(&a.partials[(size_t)bl * kMaxScal + kNormCol].im, 0.0);
   }
 }
@@ -897,7 +919,7 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     la.geo = calls[j].geo;
     la.slot0 = calls[j].v_in;
     la.basis = wss[j]->basis;
-    la.hx = wss[j]->hx;
+    la.ywin = wss[j]->ywin;
     la.m = calls[j].m;
     la.t = calls[j].t;
     la.tol = calls[j].tol;
@@ -911,9 +933,12 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
   for (int k = 0; k < c0.m; ++k) {
     const bool last = (k == c0.m - 1);
     const int i0 = last ? k : (c0.reorth ? 0 : (k > 0 ? k - 1 : 0));
+    // window start of step k+1, whose dots pass B(k) forms
+    const int i0n = (k + 1 == c0.m - 1) ? k + 1 : (c0.reorth ? 0 : k);
     for (int j = 0; j < n; ++j) {
       lb.job[j].k = k;
       lb.job[j].i0 = i0;
+      lb.job[j].i0n = i0n;
     }
     const int nwin = k - i0 + 1;
     if (c0.pe) {
@@ -923,7 +948,8 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
         const char* xk = (k == 0) ? static_cast<const char*>(calls[j].v_in)
                                   : static_cast<const char*>(wss[j]->basis) +
                                         (size_t)(k - 1) * c0.geo.D * sizeof(V);
-        if ((e = launch_hv_pe_t<R>(lb.job[j].hv, *calls[j].pe, xk, wss[j]->hx, s)) != hipSuccess)
+        void* yk = static_cast<char*>(wss[j]->ywin) + (size_t)k * c0.geo.D * sizeof(V);
+        if ((e = launch_hv_pe_t<R>(lb.job[j].hv, *calls[j].pe, xk, yk, s)) != hipSuccess)
           return e;
       }
       // x read, y written, and the orbit label and rank of every output read
@@ -938,14 +964,18 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     } else if ((e = launch_pass_r<R>(true, lb, n, s)) != hipSuccess) {
       return e;
     }
-    // algorithmic bytes: the window vectors (v_k included) are read once and
-    // y = H v_k is written (not in the last step)
-    if (prof) profiler_stop(prof, s, kProfPassA, (nwin + (last ? 0 : 1)) * vb);
+    // algorithmic bytes: v_k is read and y = H v_k is written (not in the
+    // last step; the reduced basis reads the given y instead)
+    (void)nwin;
+    if (prof) profiler_stop(prof, s, kProfPassA, (1 + ((last && !c0.pe) ? 0 : 1)) * vb);
     if (!last) {
       if (prof) profiler_start(prof, s);
       if ((e = launch_pass_r<R>(false, lb, n, s)) != hipSuccess) return e;
-      // y and the window vectors are read, v_{k+1} is written
-      if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 2) * vb);
+      // y_k and the window are read for the update, v_{k+1} is written, and
+      // the stored H v vectors of the next window are read for its dots
+      // (y_k from registers)
+      const int nd = k - i0n + 1;
+      if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 2 + (nd > 0 ? nd - 1 : 0)) * vb);
     }
   }
   const uint32_t D = c0.geo.D;
