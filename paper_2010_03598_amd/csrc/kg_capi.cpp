@@ -449,6 +449,17 @@ size_t ws_fixed_bytes() {
   return align_up(sizeof(KState), 256) + align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
 }
 
+// Tile of a standalone H v (xxz_apply), from graph-timed launches at
+// L = 12..24 over tiles of 2^8..2^12: small tiles (more blocks per compute
+// unit to hide the partner loads) up to L = 18, larger ones as the vector
+// outgrows the caches.  The Krylov passes keep make_geo's tiles, which were
+// timed as whole Krylov calls.
+int hv_tile_bits(int L, int prec) {
+  if (L <= 18) return 8;
+  if (prec == KG_C128) return (L <= 20) ? 9 : (L <= 22 ? 11 : 12);
+  return (L <= 21) ? 10 : (L == 22 ? 11 : 12);
+}
+
 Geo make_geo(int L, int prec, int tile_bits_override) {
   Geo g;
   memset(&g, 0, sizeof(g));
@@ -517,7 +528,8 @@ kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void
   KG_CHECK(check_vec(v, prec, "v"));
   KG_CHECK(check_vec(w, prec, "w"));
   if (overlap(v, w, vec_bytes(h->L, prec))) return fail(KG_EINVAL, "v and w overlap");
-  const Geo g = make_geo(h->L, prec, tile_override_from_env());
+  const int tb_env = tile_override_from_env();
+  const Geo g = make_geo(h->L, prec, tb_env >= 6 ? tb_env : hv_tile_bits(h->L, prec));
   const HvArgs a = make_hv(h, nullptr, u);
   Profiler* prof = profiler_for_launch();
   if (prof) profiler_start(prof, (hipStream_t)stream);
