@@ -46,18 +46,24 @@ def gpu_inputs(c, dtype, torch):
 
 
 def time_gradients(kg, torch, c, dtype, ckpt, steps, warmup, profile_every=0):
+    """One step = one gradient evaluation of the autograd form: F = fidelity(u)
+    (grape_forward, keeping sqrt(N) checkpoints) and F.backward() (the adjoint
+    sweep recomputing the segments and forming dF/du)."""
     h = kg.XXZ(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
     k = kg.Krylov(c.m, reorth=True)
     u, psi0, f = gpu_inputs(c, dtype, torch)
     ws = kg.Workspace(h, k, dtype)
-    states = kg.new_states(h, c.N, ckpt, dtype)
-    grad = torch.empty(c.N, dtype=torch.float64, device=u.device)
-    beta = torch.empty(2, dtype=torch.float64, device=u.device)
-    F = torch.empty((), dtype=torch.float64, device=u.device)
+    out = {}
+    # the forward's state buffer comes from torch's caching allocator: one of
+    # the same size is allocated and released here, outside any timed region
+    spare = kg.new_states(h, c.N, ckpt, dtype)
+    del spare
 
     def step():
-        kg.grape_gradient(h, u, c.dt, k, psi0, f, ckpt_every=ckpt, states=states, grad=grad,
-                          beta=beta, F=F, workspace=ws)
+        uu = u.detach().requires_grad_(True)
+        F = kg.fidelity(uu, h, c.dt, k, psi0, f, ckpt, ws)
+        F.backward()
+        out["F"], out["grad"] = F.detach(), uu.grad
 
     for i in range(warmup):
         step()
@@ -80,7 +86,8 @@ def time_gradients(kg, torch, c, dtype, ckpt, steps, warmup, profile_every=0):
     if prof is not None:
         prof.__exit__(None, None, None)
     log(f"timed {steps} steps ({dtype}) in {t1 - t0:.3f} s")
-    return (t1 - t0) / steps, float(F.cpu()), grad.cpu().numpy(), (prof.result if prof else None)
+    return ((t1 - t0) / steps, float(out["F"].cpu()), out["grad"].cpu().numpy(),
+            (prof.result if prof else None))
 
 
 def time_hv(kg, torch, L, dtype, reps=50):
@@ -491,7 +498,9 @@ def main():
         "dtype": "c64+f64",
         "data": "synthetic",
         "config": {"workload": "adjoint: open XXZ L=20 (D=2^20), J=1, Delta=1, Hc=Sx site 1, "
-                               "N=400, dt=0.05, m=20 full reorth, ckpt every 20, seed 2",
+                               "N=400, dt=0.05, m=20 full reorth, ckpt every 20, seed 2; "
+                               "step = F = fidelity(u) and F.backward() through the "
+                               "torch.autograd.Function",
                    "L": c.L, "N": c.N, "m": c.m, "dt": c.dt, "ckpt_every": ckpt,
                    "precision": "complex64 vectors, FP64 scalars", "parallelism": "1 GPU"},
         "fp64": {"value": 1.0 / sec128, "unit": "gradient evals/s", "ms_per_step": sec128 * 1e3,
