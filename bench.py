@@ -262,6 +262,25 @@ def fig2b(kg, torch, workloads, sizes, max_iter=300):
     return rows
 
 
+def batched_algorithmic_bytes(chains):
+    """Bytes the batched launch must move (complex64 vectors, 8 B per amplitude):
+    per chain, 2N-1 Krylov calls (store-all: no recomputation), each with pass A
+    reading its window and writing y (no y in the last step), pass B reading y
+    and the window and writing the next vector, and the combination reading
+    m vectors and writing one; N brackets and the overlap read two vectors."""
+    total = 0
+    for c in chains:
+        V = 8 << c.h.L
+        per_call = 0
+        for k in range(c.m):
+            last = k == c.m - 1
+            nw = 1 if last else (k + 1 if c.reorth else min(k + 1, 2))
+            per_call += (nw + (0 if last else 1)) + (0 if last else nw + 2)
+        per_call += c.m + 1
+        total += V * ((2 * c.N - 1) * per_call + 2 * c.N + 2)
+    return total
+
+
 def time_batched(kg, torch, workloads, steps=3, fp64=True):
     """The batched form on the 64-chain workload (L in 10..16, N in 50..300): the
     autotuned persistent launch (complex64 vectors, FP64 scalars; m per chain from
@@ -281,9 +300,15 @@ def time_batched(kg, torch, workloads, steps=3, fp64=True):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     b.check_status()
+    nbytes = batched_algorithmic_bytes(chains)
     out = {"chains": len(chains), "value": len(chains) / sec, "unit": "chain gradient evals/s",
            "ms_per_launch": sec * 1e3, "launches": steps, "team_cap": info["best_cap"],
-           "m": sorted({c.m for c in chains}), "element_slices": int(sum(c.N << c.h.L for c in chains))}
+           "m": sorted({c.m for c in chains}), "element_slices": int(sum(c.N << c.h.L for c in chains)),
+           "algorithmic_GB_per_launch": nbytes / 1e9,
+           "algorithmic_GBps": nbytes / sec / 1e9,
+           "frac_of_peak": nbytes / sec / 1e9 / HBM_PEAK_GBS,
+           "note": "vectors of 8-512 KiB: the working set sits in the caches, so the "
+                   "fraction of the HBM peak can exceed what HBM alone would allow"}
     if fp64:
         F32 = b.F.cpu().numpy()
         errs_g, errs_F = [], []
