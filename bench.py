@@ -431,6 +431,8 @@ def main():
     ap.add_argument("--no-pe", action="store_true", help="skip the reduced-basis leg")
     ap.add_argument("--only-pe", action="store_true",
                     help="run only the reduced-basis leg (--steps evaluations) and print its JSON")
+    ap.add_argument("--hv-only", type=int, default=0, metavar="L",
+                    help="run only the graph-timed H v at this L (complex64 and complex128)")
     ap.add_argument("--fig2b", type=str, default="", metavar="L:K,L:K,...",
                     help="run only the optimisation run-time study at these sizes, e.g. 8:4,10:4")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -460,6 +462,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.only_pe:
         print(json.dumps(time_pe(kg, torch, workloads, steps=args.steps)), flush=True)
+        return
+    if args.hv_only:
+        print(json.dumps({"hv": [time_hv(kg, torch, args.hv_only, dt, reps=20)
+                                 for dt in (torch.complex64, torch.complex128)]}), flush=True)
         return
     if args.fig2b:
         sizes = [tuple(int(v) for v in p.split(":")) for p in args.fig2b.split(",")]
