@@ -50,7 +50,8 @@
  *     status is negative and kg_last_error() names the argument.
  *   - Nothing allocates device memory; scratch comes from the caller's
  *     workspace (size from kg_workspace_bytes).  No call synchronises the
- *     stream; results are ready when the stream reaches them.
+ *     stream (kg_pe_build, which copies its tables synchronously, aside);
+ *     results are ready when the stream reaches them.
  *   - `stream` is a hipStream_t (NULL = the default stream).
  *   - Inputs are never renormalised: psi0 and the target should have unit norm.
  *   - Calls that share a workspace must not run concurrently.
