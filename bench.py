@@ -373,7 +373,6 @@ def cpu_baseline(c, budget_s=20.0):
     """The oracle (NumPy/SciPy FP64) on a bounded prefix of the same workload:
     forward Krylov propagations of the first slices, extrapolated to the
     oracle's full gradient (2N-1 propagations + N brackets, store-all)."""
-    from oracle import grape as og  # noqa: F401
     from oracle import krylov as ok
     from oracle import model as om
 
