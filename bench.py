@@ -496,6 +496,9 @@ def main():
     per_launch_s = d["ms"] / d["launches"] * 1e-3
     bytes_per_launch = d["bytes"] / d["launches"]
     achieved = bytes_per_launch / per_launch_s / 1e9
+    # every sampled record stands for profile_every launches of its class, so
+    # the sampled bytes scale to the whole step's algorithmic bytes
+    step_bytes = sum(v["bytes"] for v in prof.values()) * args.profile_every / args.steps
     classes = {k: {"launches_timed": v["launches"],
                    "avg_us": (v["ms"] / v["launches"] * 1e3) if v["launches"] else None,
                    "avg_algorithmic_GB": (v["bytes"] / v["launches"] / 1e9) if v["launches"] else None,
@@ -544,7 +547,13 @@ def main():
                      "traffic": recorded_traffic(dom),
                      "traffic_source": os.path.relpath(TRAFFIC_FILE, ROOT),
                      "avg_us": per_launch_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
-                     "sampled_launches": d["launches"]},
+                     "sampled_launches": d["launches"],
+                     "concurrency": "the costate sweep's launches run beside the segment "
+                                    "recomputation's, on a second stream: each launch's "
+                                    "duration includes the other stream's share of the chip",
+                     "step_algorithmic_GB": step_bytes / 1e9,
+                     "step_achieved": step_bytes / sec64 / 1e9,
+                     "step_frac": step_bytes / sec64 / 1e9 / HBM_PEAK_GBS},
         "kernels": classes,
         "batched": bat,
         "reduced_basis": pe,

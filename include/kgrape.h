@@ -52,7 +52,13 @@
  *     workspace (size from kg_workspace_bytes).  No call synchronises the
  *     stream (kg_pe_build, which copies its tables synchronously, aside);
  *     results are ready when the stream reaches them.
- *   - `stream` is a hipStream_t (NULL = the default stream).
+ *   - `stream` is a hipStream_t (NULL = the default stream).  The gradient
+ *     calls with checkpoints (more than two segments) run the recomputation of
+ *     earlier segments on a second stream of the library's own (one per host
+ *     thread and device, default priority), forked from `stream` with an event
+ *     and joined back to it before any result is read, so the call stays
+ *     ordered on `stream` and a capture of `stream` takes in both branches.
+ *     Setting KG_ONE_STREAM in the environment keeps all work on `stream`.
  *   - Inputs are never renormalised: psi0 and the target should have unit norm.
  *   - Calls that share a workspace must not run concurrently.
  *   - Lanczos breakdown (an invariant Krylov space) is not an error: the call
@@ -99,7 +105,10 @@ typedef struct kg_xxz {
  * Gram-Schmidt, App. A), 0 = against the last two only (plain Lanczos,
  * Algorithm 2).  breakdown_tol: relative threshold; the basis stops at step k
  * when ||w_{k+1}|| <= tol * max(1, max_{i<=k}(|alpha_i| + beta_i)); 0 selects
- * 64 * (unit roundoff of the vector type). */
+ * 64 * (unit roundoff of the vector type).  The projected exponential
+ * exp(-i t T) e_1 is evaluated for |t| ||T||_inf <= 32768; beyond that, or for
+ * a non-finite T (for example a non-finite control amplitude), the call's
+ * output vector is NaN. */
 typedef struct kg_krylov {
   int32_t m;
   int32_t reorth;
@@ -114,7 +123,7 @@ int32_t kg_version(void);
 
 /* Bytes of workspace that krylov_expv, grape_forward and grape_gradient need
  * for this chain, Krylov dimension and precision: two Krylov slots (scalars,
- * reduction partials, m-1 basis vectors and the m vectors H v_i each; the
+ * reduction partials, m-1 basis vectors and one vector H v_k each; the
  * second slot advances the segment recomputation beside the backward sweep)
  * and one costate vector.
  * Returns 0 for invalid arguments. */
@@ -139,7 +148,8 @@ kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void
  * (App. A, Algorithm 2) and the exponential of the tridiagonal projection
  * (Eqs. A1-A3): v_out = ||v_in|| V^T exp(-i t T) e_1.  v_out may equal v_in
  * (in place); otherwise they must not overlap.  A zero input gives a zero
- * output (m_eff = 0).  m_eff_dev (nullable): device int32 that receives the
+ * output (m_eff = 0), an input with a non-finite amplitude a NaN output
+ * (m_eff = 1).  m_eff_dev (nullable): device int32 that receives the
  * dimension reached.  Errors: KG_EINVAL, KG_EWORKSPACE, KG_EDEVICE. */
 kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, int32_t prec,
                       const void* v_in, void* v_out, void* ws, size_t ws_bytes,

@@ -224,10 +224,18 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
       bool zero = false;
       if (k == 0) {
         const double nn = tot[nwin].re;
-        if (!(nn > 0.0)) {
+        if (nn == 0.0) {
           zero = true;
           K.beta0 = 0.0;
           K.m_eff = 0;
+          K.done = 1;
+        } else if (!(nn > 0.0)) {
+          // a non-finite input: exp(0) times NaN, so the output is NaN
+          zero = true;
+          K.beta0 = NAN;
+          K.m_eff = 1;
+          K.alpha[0] = 0.0;
+          K.scale[0] = 1.0;
           K.done = 1;
         } else {
           K.beta0 = sqrt(nn);

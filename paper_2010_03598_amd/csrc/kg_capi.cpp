@@ -132,10 +132,10 @@ HvArgs make_hv(const kg_xxz* h, const double* u_ptr, double u_val) {
 size_t vbytes(uint64_t D, int32_t prec) { return (size_t)D * (prec == KG_C128 ? 16 : 8); }
 
 // A Krylov slot: scalars, reduction partials, basis vectors 1..m-1 and the
-// m vectors y_i = H v_i.
+// vector y_k = H v_k of the running step.
 size_t slot_bytes_d(uint64_t D, const kg_krylov* k, int32_t prec) {
   return ws_fixed_bytes() + align_up(vbytes(D, prec) * (size_t)(k->m - 1), 256) +
-         align_up(vbytes(D, prec) * (size_t)k->m, 256);
+         align_up(vbytes(D, prec), 256);
 }
 
 // workspace of vectors of D amplitudes; `extended` adds the two node vectors
@@ -176,7 +176,7 @@ kg_status carve_d(void* ws, size_t ws_bytes, uint64_t D, const kg_krylov* k, int
     q += align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
     o->basis = q;
     q += align_up(vbytes(D, prec) * (size_t)(k->m - 1), 256);
-    o->ywin = q;
+    o->yk = q;
     o->lam = p + 2 * slot_bytes_d(D, k, prec);
     o->node_a = extended ? static_cast<char*>(o->lam) + vb : nullptr;
     o->node_b = extended ? static_cast<char*>(o->lam) + 2 * vb : nullptr;
@@ -272,6 +272,48 @@ kg_status forward_sweep(const SweepArgs& a, const States& S, double* F_dev, doub
   return KG_OK;
 }
 
+// The backward sweep runs the segment recomputation on a second stream beside
+// the costate propagation: the two chains of Krylov calls are independent
+// inside a segment, and on separate streams one chain's reduction tails
+// overlap the other's passes (paired launches, which put both calls in the
+// same kernels, are no faster than two single ones).  Resources are created
+// once per host thread and device, at the default priority; events fork the
+// side stream off the caller's stream and join it back, so the work is
+// ordered for the caller and a stream capture takes in both branches.
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+// nullptr: use paired launches on the caller's stream instead
+const SideStream* side_stream(hipStream_t caller) {
+  static thread_local SideStream per_device[64];
+  if (getenv("KG_ONE_STREAM")) return nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  SideStream& r = per_device[dev];
+  if (!r.s) {
+    // creating resources while the caller's stream is being captured is not
+    // allowed everywhere: fall back to paired launches for that call
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(caller, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+      return nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t ef = nullptr, ej = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&ef, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ej, hipEventDisableTiming) != hipSuccess) {
+      if (ef) (void)hipEventDestroy(ef);
+      (void)hipStreamDestroy(st);
+      return nullptr;
+    }
+    r.s = st;
+    r.fork = ef;
+    r.join = ej;
+  }
+  return &r;
+}
+
 // Nodes of the in-slice quadrature: times s_q in (0, dt) and weights w_q.
 struct Quadrature {
   int n = 0;
@@ -299,7 +341,16 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
   const bool acc = col > 0;
   const uint32_t* pe_reps = a.pe ? a.pe->reps : nullptr;
   const void* lam = a.target;
+  // (the quadrature's node states use the second slot on the caller's stream)
+  const bool quad = Q && Q->n > 0;
+  const SideStream* side = (S.c > 0 && S.nseg > 2 && !quad) ? side_stream(a.stream) : nullptr;
   for (int q = S.nseg - 1; q >= 0; --q) {
+    if (side) {
+      // the recomputation of this segment's loop overwrites the buffer that the
+      // previous segment's brackets read: start it after them
+      KG_HIP(hipEventRecord(side->fork, a.stream), "backward sweep fork");
+      KG_HIP(hipStreamWaitEvent(side->s, side->fork, 0), "backward sweep fork");
+    }
     const int cs = (S.c == 0) ? 0 : q * S.c;
     const int len = (S.c == 0) ? a.N : ((a.N - cs < S.c) ? a.N - cs : S.c);
     // segment q-1 is recomputed beside this segment's backward sweep unless the
@@ -349,7 +400,12 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
         if (recompute && re_i <= S.c - 1) {
           const int jr = rq * S.c + re_i;
           const KrylovCall cr = krylov_call(a, jr, a.dt, re_in, S.at(jr));
-          KG_HIP(launch_krylov_pair(cb, a.ws, cr, a.ws1, a.stream), "backward sweep");
+          if (side) {
+            KG_HIP(launch_krylov(cb, a.ws, a.stream), "backward sweep");
+            KG_HIP(launch_krylov(cr, a.ws1, side->s), "segment recomputation");
+          } else {
+            KG_HIP(launch_krylov_pair(cb, a.ws, cr, a.ws1, a.stream), "backward sweep");
+          }
           re_in = S.at(jr);
           ++re_i;
         } else {
@@ -361,8 +417,13 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
     for (; recompute && re_i <= S.c - 1; ++re_i) {
       const int jr = rq * S.c + re_i;
       const KrylovCall cr = krylov_call(a, jr, a.dt, re_in, S.at(jr));
-      KG_HIP(launch_krylov(cr, a.ws1, a.stream), "segment recomputation");
+      KG_HIP(launch_krylov(cr, a.ws1, side ? side->s : a.stream), "segment recomputation");
       re_in = S.at(jr);
+    }
+    if (side) {
+      // the next segment's brackets read the states recomputed here
+      KG_HIP(hipEventRecord(side->join, side->s), "backward sweep join");
+      KG_HIP(hipStreamWaitEvent(a.stream, side->join, 0), "backward sweep join");
     }
   }
   if (centred) {

@@ -117,17 +117,20 @@ __device__ __forceinline__ void complete_stores() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Columns j of a partials table summed over `cnt` rows: j < ns from `rows`
-// (row stride kMaxScal), j == ns (when `xrows` is given) from column 0 of
-// `xrows` (same row stride).  Lane l adds rows l, l+64, ... in order, then a
-// fixed butterfly; the block's wavefronts share the columns.  Loads are
-// device-scope, and the loads of a batch of JB columns (RPL rows per lane
-// each) are all issued before any is used: one memory round trip per batch.
+// Columns j of a partials table summed over `cnt` rows.  The table is column
+// major (column stride kPartialRows, one row per block): j < ns from `cols`,
+// j == ns (when `xcol` is given) from `xcol`.  Columns j < c_plain and `xcol`
+// were written by an earlier launch and are read with plain 16-byte loads;
+// the others, written by blocks of this launch, with device-scope loads.
+// Lane l adds rows l, l+64, ... in order, then a fixed butterfly; the block's
+// wavefronts share the columns.  The loads of a batch of JB columns (RPL rows
+// per lane each) are all issued before any is used: one memory round trip per
+// batch.
 template <int RPL, int JB>
-__device__ void sum_rows_t(const cplx_d* rows, uint32_t cnt, int ns, const cplx_d* xrows,
-                           cplx_d* tot) {
+__device__ void sum_rows_t(const cplx_d* cols, uint32_t cnt, int ns, const cplx_d* xcol,
+                           int c_plain, cplx_d* tot) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const int nc = ns + (xrows ? 1 : 0);
+  const int nc = ns + (xcol ? 1 : 0);
   for (int j0 = wv; j0 < nc; j0 += nw * JB) {
     double re[JB], im[JB];
 #pragma unroll
@@ -137,13 +140,21 @@ __device__ void sum_rows_t(const cplx_d* rows, uint32_t cnt, int ns, const cplx_
 #pragma unroll
       for (int c = 0; c < JB; ++c) {
         const int j = j0 + c * nw;
-        const cplx_d* base = (j < ns) ? rows + j : xrows;
+        const cplx_d* base = (j < ns) ? cols + (size_t)j * kPartialRows : xcol;
+        const bool plain = j < c_plain || j == ns;
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
           const uint32_t r = min(b0 + q * 64 + lane, cnt - 1);
-          const cplx_d* p = base + (size_t)r * kMaxScal;
-          pr[c][q] = (j < nc) ? ld_agent(&p->re) : 0.0;
-          pi[c][q] = (j < nc) ? ld_agent(&p->im) : 0.0;
+          if (j >= nc) {
+            pr[c][q] = pi[c][q] = 0.0;
+          } else if (plain) {
+            const cplx_d v = base[r];
+            pr[c][q] = v.re;
+            pi[c][q] = v.im;
+          } else {
+            pr[c][q] = ld_agent(&base[r].re);
+            pi[c][q] = ld_agent(&base[r].im);
+          }
         }
       }
 #pragma unroll
@@ -168,16 +179,16 @@ __device__ void sum_rows_t(const cplx_d* rows, uint32_t cnt, int ns, const cplx_
 
 // sum_rows_t with the batch shape chosen for the row count: about 16 loads
 // in flight per lane.
-__device__ void sum_rows(const cplx_d* rows, uint32_t cnt, int ns, const cplx_d* xrows,
+__device__ void sum_rows(const cplx_d* cols, uint32_t cnt, int ns, const cplx_d* xcol, int c_plain,
                          cplx_d* tot) {
   if (cnt <= 64) {
-    sum_rows_t<1, 8>(rows, cnt, ns, xrows, tot);
+    sum_rows_t<1, 8>(cols, cnt, ns, xcol, c_plain, tot);
   } else if (cnt <= 128) {
-    sum_rows_t<2, 4>(rows, cnt, ns, xrows, tot);
+    sum_rows_t<2, 4>(cols, cnt, ns, xcol, c_plain, tot);
   } else if (cnt <= 256) {
-    sum_rows_t<4, 2>(rows, cnt, ns, xrows, tot);
+    sum_rows_t<4, 2>(cols, cnt, ns, xcol, c_plain, tot);
   } else {
-    sum_rows_t<8, 1>(rows, cnt, ns, xrows, tot);
+    sum_rows_t<8, 1>(cols, cnt, ns, xcol, c_plain, tot);
   }
 }
 
@@ -208,56 +219,55 @@ constexpr uint32_t kGroup = 64;        // blocks per group of the two-level redu
 // to arrive, with the grid totals in `tot`.  Up to kReduceFlat blocks the last
 // block adds all partials; larger grids add groups of kGroup blocks first (the
 // last block of each group), then the groups.  The order is fixed, so results
-// do not depend on which block arrives last.  When `xrows` is given (one
-// value per block in column 0, row stride kMaxScal, written by an earlier
-// kernel) its sum over the G blocks lands in tot[ns] by the same scheme.
-// With c0 > 0 this launch formed only columns [c0, ns): each block writes
-// those, and columns [0, c0) of the same rows were written by an earlier
-// kernel; the sums cover all columns.
+// do not depend on which block arrives last.  The partials table is column
+// major: value (column j, block b) at partials[j * kPartialRows + b].  When
+// `xcol` is given (one value per block, written by an earlier launch) its sum
+// over the G blocks lands in tot[ns] by the same scheme.  With c0 > 0 this
+// launch formed only columns [c0, ns): each block writes those, and columns
+// [0, c0) were written by an earlier launch; the sums cover all columns.
 //
-// The partials travel only through device-scope (sc1) stores and loads, which
-// are coherent across the XCDs' L2 caches; the stores are waited for before
-// the arrival counter is incremented.  No device-wide fence is needed, so the
-// L2 caches are never written back or invalidated here.  counters[0] counts
-// the top level, counters[1 + g] group g.
+// The partials of this launch travel only through device-scope (sc1) stores
+// and loads, which are coherent across the XCDs' L2 caches; the stores are
+// waited for before the arrival counter is incremented.  No device-wide fence
+// is needed, so the L2 caches are never written back or invalidated here.
+// counters[0] counts the top level, counters[1 + g] group g.
 __device__ bool grid_reduce(cplx_d* tot, int ns, cplx_d* partials, uint32_t* counters, uint32_t b,
-                            uint32_t G, const cplx_d* xrows = nullptr, int c0 = 0) {
+                            uint32_t G, const cplx_d* xcol = nullptr, int c0 = 0) {
   const int lane = threadIdx.x & 63;
   if (G == 1) {
-    for (int j = threadIdx.x; j < c0; j += blockDim.x)
-      tot[j] = cplx_d{ld_agent(&partials[j].re), ld_agent(&partials[j].im)};
-    if (xrows && threadIdx.x == 0) tot[ns] = cplx_d{ld_agent(&xrows[0].re), ld_agent(&xrows[0].im)};
+    for (int j = threadIdx.x; j < c0; j += blockDim.x) tot[j] = partials[(size_t)j * kPartialRows];
+    if (xcol && threadIdx.x == 0) tot[ns] = xcol[0];
     __syncthreads();
     return true;
   }
   if ((threadIdx.x >> 6) == 0) {
     for (int j = c0 + lane; j < ns; j += 64) {
-      st_agent(&partials[(size_t)b * kMaxScal + j].re, tot[j].re);
-      st_agent(&partials[(size_t)b * kMaxScal + j].im, tot[j].im);
+      st_agent(&partials[(size_t)j * kPartialRows + b].re, tot[j].re);
+      st_agent(&partials[(size_t)j * kPartialRows + b].im, tot[j].im);
     }
   }
   if (G <= kReduceFlat) {
     if (!arrive_last(&counters[0], G)) return false;
-    sum_rows(partials, G, ns, xrows, tot);
+    sum_rows(partials, G, ns, xcol, c0, tot);
     __syncthreads();
     return true;
   }
   const uint32_t grp = b / kGroup, ngrp = (G + kGroup - 1) / kGroup;
   const uint32_t gsize = min(kGroup, G - grp * kGroup);
   if (!arrive_last(&counters[1 + grp], gsize)) return false;
-  sum_rows(partials + (size_t)grp * kGroup * kMaxScal, gsize, ns,
-           xrows ? xrows + (size_t)grp * kGroup * kMaxScal : nullptr, tot);
+  sum_rows(partials + (size_t)grp * kGroup, gsize, ns, xcol ? xcol + (size_t)grp * kGroup : nullptr,
+           c0, tot);
   __syncthreads();
-  // group totals (and the extra column's) go to rows [G, G + ngrp) of the table
-  const int nc = ns + (xrows ? 1 : 0);
+  // group totals (and the extra column's, in column ns) go to rows [G, G + ngrp)
+  const int nc = ns + (xcol ? 1 : 0);
   if ((threadIdx.x >> 6) == 0) {
     for (int j = lane; j < nc; j += 64) {
-      st_agent(&partials[(size_t)(G + grp) * kMaxScal + j].re, tot[j].re);
-      st_agent(&partials[(size_t)(G + grp) * kMaxScal + j].im, tot[j].im);
+      st_agent(&partials[(size_t)j * kPartialRows + G + grp].re, tot[j].re);
+      st_agent(&partials[(size_t)j * kPartialRows + G + grp].im, tot[j].im);
     }
   }
   if (!arrive_last(&counters[0], ngrp)) return false;
-  sum_rows(partials + (size_t)G * kMaxScal, ngrp, nc, nullptr, tot);
+  sum_rows(partials + G, ngrp, nc, nullptr, 0, tot);
   __syncthreads();
   return true;
 }
@@ -282,11 +292,19 @@ __device__ void block_totals(const cplx_d* wacc, int ns, cplx_d* tot, int c0 = 0
 // hi = T[i][i+1]; rows past the dimension are zero).  Scaled Taylor series:
 // the step is split into nsub pieces with |t/nsub| ||T||_inf <= 1/2 and each
 // piece uses 16 terms (remainder below 2^-17/17! relative).
+// Beyond kMaxSubsteps pieces (|t| ||T||_inf > kMaxSubsteps / 2, or a
+// non-finite T or t) the result is NaN: the loop stays bounded whatever the
+// entries.
+constexpr double kMaxSubsteps = 65536.0;
 __device__ void tri_exp_wave(double a, double lo, double hi, double t, double& cr, double& ci) {
   const int lane = threadIdx.x & 63;
   const double nrm = wave_max(fabs(a) + lo + hi);
-  int nsub = (int)ceil(fabs(t) * nrm * 2.0);
-  if (nsub < 1) nsub = 1;
+  const double want = ceil(fabs(t) * nrm * 2.0);
+  if (!(want <= kMaxSubsteps)) {
+    cr = ci = NAN;
+    return;
+  }
+  const int nsub = want < 1.0 ? 1 : (int)want;
   const double tau = t / (double)nsub;
   double yr = (lane == 0) ? 1.0 : 0.0, yi = 0.0;
   for (int step = 0; step < nsub; ++step) {

@@ -9,7 +9,9 @@
 namespace kg {
 
 constexpr int kMaxM = 64;          // largest Krylov dimension
-constexpr int kMaxScal = kMaxM + 2;  // reduction scalars per pass (window + norm + spare)
+// reduction scalars per pass: two per window vector, two of the new vector,
+// the norm carried from pass B to pass A
+constexpr int kMaxScal = 2 * kMaxM + 3;
 constexpr int kMaxGrid = 2048;     // largest grid of the reducing kernels
 constexpr int kPartialRows = kMaxGrid + kMaxGrid / 64;  // block rows + group rows
 
@@ -25,6 +27,11 @@ struct KState {
   double scale[kMaxM + 1];
   cplx_d coef[kMaxM];     // projection coefficients of the current step (window order)
   cplx_d dcomb[kMaxM];    // combination coefficients beta0 * c_j * scale_j
+  // c^(i)_i and c^(i)_{i-1} of every step i (projection coefficients on the
+  // stored vector itself and on its predecessor)
+  cplx_d cdiag[kMaxM];
+  cplx_d csub[kMaxM];
+  cplx_d gcol[2][kMaxM];  // measured Gram columns <u_j|u_p>, by the parity of p
   double beta0;
   double normT;           // max_{i<=k}(|alpha_i| + offd_i)
   int32_t m_eff;
@@ -66,9 +73,9 @@ int stream_grid(uint32_t D);
 
 struct Workspace {         // carved from the caller's workspace
   KState* st;
-  cplx_d* partials;        // [kPartialRows][kMaxScal]
+  cplx_d* partials;        // [kMaxScal][kPartialRows]: column major, one row per block
   void* basis;             // m-1 vectors (stored Krylov vectors 1..m-1)
-  void* ywin;              // m vectors: y_i = H v_i of the running basis
+  void* yk;                // one vector: y_k = H v_k of the running step
   void* lam;               // one vector (costate)
   void* node_a;            // quadrature workspaces only: psi at a node
   void* node_b;            //   and lambda at the node

@@ -181,11 +181,13 @@ struct LzArgs {
   Geo geo;
   const void* slot0;  // stored vector 0: the input of the Krylov call
   void* basis;        // stored vectors 1..m-1
-  void* ywin;         // y_i = H v_i, i = 0..m-1 (y_k written by pass A(k))
+  void* yk;           // y_k = H v_k: written by pass A(k), read by pass B(k)
   int32_t k;          // basis step
   int32_t i0;         // first index of the projection window [i0, k]
   int32_t m;
-  int32_t i0n;        // pass B(k): first index of the next step's window
+  int32_t i0n;        // first index of the next step's window
+  int32_t i0p;        // first index of the previous step's window
+  int32_t pad_;
   double t;
   double tol;
   KState* st;
@@ -197,7 +199,8 @@ constexpr int kMaxJobs = 2;
 // Column of the partials table that carries pass B's norm parts to the next
 // pass A (pass A's own partials use columns 0..m <= kMaxM).
 constexpr int kNormCol = kMaxScal - 1;
-static_assert(kNormCol > kMaxM, "norm column overlaps the window columns");
+static_assert(kNormCol > 2 * kMaxM + 1, "norm column overlaps the window columns");
+static_assert(kMaxM <= 64, "a window is held one vector per lane of a wavefront");
 
 // Independent Krylov calls of the same shape advanced by the same launches:
 // blocks [j*G, (j+1)*G) serve job j.
@@ -211,10 +214,6 @@ __device__ __forceinline__ const V* slot_ptr(const LzArgs& a, int i) {
                 : reinterpret_cast<const V*>(a.basis) + (size_t)(i - 1) * a.geo.D;
 }
 
-template <typename V>
-__device__ __forceinline__ V* y_ptr(const LzArgs& a, int i) {
-  return reinterpret_cast<V*>(a.ywin) + (size_t)i * a.geo.D;
-}
 
 // Scalar tail of a basis: exp(-itT) e_1 on wavefront 0 of the finishing block
 // and the combination coefficients dcomb_j = beta0 c_j scale_j.  Values this
@@ -260,12 +259,88 @@ __device__ __forceinline__ void store_y(const Tile<R, RB>& T, typename VT<R>::T*
   }
 }
 
+// The window dots of step k, d_i = <u_i|H u_k> for i in [i0, k), on wavefront
+// 0 of the finishing block of pass A(k) (lane l: i = i0 + l), without reading
+// a window vector.  u_i are the stored (unnormalised) vectors, s_i = 1/||u_i||
+// and c^(i) the projection coefficients of step i, so that pass B(i) stored
+//   u_{i+1} = s_i y_i - sum_j c^(i)_j u_j,   y_i = H u_i.
+// As H is Hermitian, d_i = <y_i|u_k> = (e_{i+1} + sum_j conj(c^(i)_j) e_j) / s_i
+// with e_j = <u_j|u_k>; and with p = k-1,
+//   e_j = s_p <u_j|y_p> - sum_l c^(p)_l G_jl,   e_k = ||u_k||^2,
+// where G_jl = <u_j|u_l>.  Pass B(p) measured <u_j|y_p> (columns [0, nb)) and
+// G_jp (columns [nb, 2nb)) on the stored vectors, and pass B(p-1) the column
+// G_{j,p-1}.  In a re-orthogonalised basis the entries G_jl (j != l) and the
+// coefficients c^(i)_j (j < i-1) are of the order of the rounding error, so
+// the products of two of them are dropped: the sums keep l in {j, p-1, p} and
+// j in {i-1, i}, which are all the terms of the three-term window.  In exact
+// arithmetic the dots are exact either way (G is then diagonal).
+__device__ cplx_d window_dots(const LzArgs& a, const cplx_d* tot, int nb, double ekk) {
+  KState* st = a.st;
+  const int lane = threadIdx.x & 63;
+  const int p = a.k - 1, ip = a.i0p;
+  const int j = ip + lane;
+  const bool has_pm = p - 1 >= ip;
+  // step p's coefficients (still in coef) and the stored scalars, read first
+  const cplx_d cp = st->coef[p - ip];
+  const cplx_d cpm = has_pm ? st->coef[p - 1 - ip] : cplx_d{0.0, 0.0};
+  const double sp = st->scale[p];
+  double er = 0.0, ei = 0.0;
+  if (lane < nb) {
+    const cplx_d cj = st->coef[lane];
+    const double sj = st->scale[j];
+    const cplx_d gjp = tot[nb + lane];
+    cplx_d gjm{0.0, 0.0};   // G_{j,p-1}
+    if (has_pm) {
+      if (j == p) {
+        gjm = tot[nb + (p - 1 - ip)];
+        gjm.im = -gjm.im;
+      } else if (j == p - 1) {
+        gjm = cplx_d{1.0 / (sj * sj), 0.0};
+      } else {
+        gjm = st->gcol[(p - 1) & 1][j];
+      }
+    }
+    er = sp * tot[lane].re - (cp.re * gjp.re - cp.im * gjp.im) -
+         (cpm.re * gjm.re - cpm.im * gjm.im);
+    ei = sp * tot[lane].im - (cp.re * gjp.im + cp.im * gjp.re) -
+         (cpm.re * gjm.im + cpm.im * gjm.re);
+    if (j < p - 1) {
+      const double gjj = 1.0 / (sj * sj);
+      er -= cj.re * gjj;
+      ei -= cj.im * gjj;
+    }
+    st->gcol[p & 1][j] = gjp;   // for step k+1
+  } else if (lane == nb) {
+    er = ekk;   // j = k
+  }
+  // lane l: i = i0 + l takes e_{i+1}, e_i and e_{i-1} from lanes i+1-ip, i-ip, i-1-ip
+  const int i = a.i0 + lane;
+  const bool want = i < a.k;
+  const int src = i - ip;
+  const double e1r = __shfl(er, min(max(src + 1, 0), 63), 64);
+  const double e1i = __shfl(ei, min(max(src + 1, 0), 63), 64);
+  const double e0r = __shfl(er, min(max(src, 0), 63), 64);
+  const double e0i = __shfl(ei, min(max(src, 0), 63), 64);
+  const double emr = __shfl(er, min(max(src - 1, 0), 63), 64);
+  const double emi = __shfl(ei, min(max(src - 1, 0), 63), 64);
+  if (!want) return cplx_d{0.0, 0.0};
+  const cplx_d cd = st->cdiag[i];
+  double dr = e1r + cd.re * e0r + cd.im * e0i;
+  double di = e1i + cd.re * e0i - cd.im * e0r;
+  if (i >= 1 && i - 1 >= ip) {
+    const cplx_d cs = st->csub[i];
+    dr += cs.re * emr + cs.im * emi;
+    di += cs.re * emi - cs.im * emr;
+  }
+  const double si = st->scale[i];
+  return cplx_d{dr / si, di / si};
+}
+
 // Pass A(k): y = H v_k, stored as y_k (the last step keeps it in registers),
-// and this block's parts of <v_k|y> and ||v_k||^2 (window columns nwin-1 and
-// nwin).  The window dots <v_i|y> for i in [i0, k) need no window reads here:
-// pass B(k-1) formed them as <y_i|w> (H is Hermitian and v_k = w) in columns
-// 0..nwin-2 of the same partials rows.  The finishing block adds the columns
-// of both passes and pass B's norm parts, then runs the scalar update.
+// and this block's parts of <v_k|y> and ||v_k||^2 (columns 2nb and 2nb+1,
+// after pass B(k-1)'s 2nb measured columns in the same partials rows).  The
+// finishing block adds the columns of both passes and pass B's norm parts,
+// derives the window dots (window_dots) and runs the scalar update.
 // kYIn: y_k was written by a separate H v kernel (the reduced basis); the pass
 // then loads it instead of forming it on the tile.
 template <typename R, int RB, bool kYIn = false>
@@ -277,7 +352,11 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   __shared__ cplx_d tot[kMaxScal];
 
   const int nwin = a.k - a.i0 + 1;
-  const int ns = nwin + 1;
+  // pass B(k-1)'s window (two measured columns per vector), if step k has
+  // window dots
+  const int nb = (a.k > 0 && a.i0 < a.k) ? a.k - a.i0p : 0;
+  const int ca = 2 * nb;
+  const int ns = ca + 2;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
   const uint32_t eb = lane | (wv << (6 + RB));
@@ -285,7 +364,7 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
 
   const double u = control_value(a.hv);
   const V* x = slot_ptr<V>(a, a.k);
-  V* yk = y_ptr<V>(a, a.k);
+  V* yk = reinterpret_cast<V*>(a.yk);
   const uint32_t iters = a.geo.ntiles / G;
   Tile<R, RB> T;
   for (uint32_t it = 0; it < iters; ++it) {
@@ -327,14 +406,14 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   __syncthreads();
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
   if (lane == 0) {
-    wacc[wv * kMaxScal + nwin - 1] = cplx_d{acc_re, acc_im};
-    wacc[wv * kMaxScal + nwin] = cplx_d{acc_nn, 0.0};
+    wacc[wv * kMaxScal + ca] = cplx_d{acc_re, acc_im};
+    wacc[wv * kMaxScal + ca + 1] = cplx_d{acc_nn, 0.0};
   }
   __syncthreads();
-  block_totals(wacc, ns, tot, nwin - 1);
-  // columns [0, nwin-1) come from pass B(k-1); for k >= 1 its norm parts land in tot[ns]
+  block_totals(wacc, ns, tot, ca);
+  // columns [0, ca) come from pass B(k-1); for k >= 1 its norm parts land in tot[ns]
   if (!grid_reduce(tot, ns, a.partials, a.st->counters, bl, G,
-                   a.k > 0 ? a.partials + kNormCol : nullptr, nwin - 1))
+                   a.k > 0 ? a.partials + (size_t)kNormCol * kPartialRows : nullptr, ca))
     return;
   if (threadIdx.x >= 64) return;
 
@@ -344,12 +423,15 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   const int k = a.k;
   double sk, b0 = NAN, s0 = NAN, bk = 0.0;
   if (k == 0) {
-    const double nn = tot[nwin].re;
+    const double nn = tot[ca + 1].re;
     if (!(nn > 0.0)) {
+      // a zero input gives a zero output; a non-finite one a NaN output
+      const bool zero = nn == 0.0;
       if (lane0 == 0) {
-        st->beta0 = 0.0;
+        st->beta0 = zero ? 0.0 : NAN;
         st->normT = 0.0;
-        st->m_eff = 0;
+        st->m_eff = zero ? 0 : 1;
+        st->dcomb[0] = cplx_d{NAN, NAN};
         st->done = 1;
       }
       return;
@@ -377,13 +459,19 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
       st->scale[k] = sk;
     }
   }
-  for (int l = lane0; l < nwin; l += 64) {
-    const int i = a.i0 + l;
+  // lane l: window index i0 + l (a window holds at most kMaxM <= 64 vectors)
+  const cplx_d d = (nb > 0) ? window_dots(a, tot, nb, tot[ns].re) : cplx_d{0.0, 0.0};
+  if (lane0 < nwin) {
+    const int i = a.i0 + lane0;
     const double si = (i == k) ? sk : st->scale[i];
     const double f = si * sk;
-    st->coef[l] = cplx_d{tot[l].re * f * si, tot[l].im * f * si};
+    const cplx_d t = (i == k) ? tot[ca] : d;
+    const cplx_d c{t.re * f * si, t.im * f * si};
+    st->coef[lane0] = c;
+    if (i == k) st->cdiag[k] = c;
+    if (i == k - 1) st->csub[k] = c;
   }
-  const double alpha = tot[nwin - 1].re * sk * sk;
+  const double alpha = tot[ca].re * sk * sk;
   const double offk = (k == 0) ? 0.0 : bk;
   const double prevT = (k == 0) ? 0.0 : st->normT;
   const double normT = fmax(prevT, fabs(alpha) + offk);
@@ -418,8 +506,9 @@ __global__ void __launch_bounds__(1024) k_pass_a_y(LzBatch B) {
 
 // Pass B(k): w = s_k y_k - sum_i c_i v_i over the window [i0, k] (FP64), stored
 // unnormalised as v_{k+1}, with this block's part of ||w||^2 (column kNormCol)
-// and of the next step's window dots <v_i|H w> = <y_i|w>, i in [i0n, k]
-// (columns 0..k-i0n), against the stored H v vectors and the stored w.
+// and, when step k+1 has window dots, of <v_i|y_k> (columns [0, nb)) and
+// <v_i|v_k> (columns [nb, 2nb)) for i in the window: the operands are already
+// in registers for the update, and pass A(k+1) derives its dots from them.
 template <typename R, int RB>
 __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
@@ -431,13 +520,14 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
   const uint32_t eb = lane | (wv << (6 + RB));
-  const int nd = a.k - a.i0n + 1;   // next step's dots formed here (0 before the last step)
+  const int nb = (a.i0n <= a.k) ? a.k - a.i0 + 1 : 0;
   double acc_nn = 0.0;
-  double acc_re = 0.0, acc_im = 0.0;   // lane l: dot of column l
+  // lane l: the measurements of window vector i0 + l
+  double aar = 0.0, aai = 0.0, agr = 0.0, agi = 0.0;
 
   const KState* st = a.st;
   const V* x = slot_ptr<V>(a, a.k);
-  const V* yv = y_ptr<V>(a, a.k);
+  const V* yv = reinterpret_cast<const V*>(a.yk);
   V* out = reinterpret_cast<V*>(a.basis) + (size_t)a.k * a.geo.D;
   const uint32_t iters = a.geo.ntiles / G;
   // same block-to-tile map as pass A, so y is read back from the L2 that wrote it
@@ -464,6 +554,25 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
         zi[r] = sk * (double)yo[r].y - (c.re * vi + c.im * vr);
       }
     }
+    if (nb) {
+      // <v_k|y_k> and ||v_k||^2
+      double sr = 0.0, si = 0.0, gr = 0.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const double vr = xo[r].x, vi = xo[r].y, yr = yo[r].x, yi = yo[r].y;
+        sr += vr * yr + vi * yi;
+        si += vr * yi - vi * yr;
+        gr += vr * vr + vi * vi;
+      }
+      sr = wave_sum(sr);
+      si = wave_sum(si);
+      gr = wave_sum(gr);
+      if ((int)lane == a.k - a.i0) {
+        aar += sr;
+        aai += si;
+        agr += gr;
+      }
+    }
     // window vectors other than v_k, NW per round trip
     for (int i = a.i0; i < a.k; i += NW) {
       V q[NW][NR];
@@ -483,16 +592,34 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
       for (int j = 0; j < NW; ++j) {
         if (i + j < a.k) {
           const cplx_d c = st->coef[i + j - a.i0];
+          double sr = 0.0, si = 0.0, gr = 0.0, gi = 0.0;
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
             const double vr = q[j][r].x, vi = q[j][r].y;
             zr[r] -= c.re * vr - c.im * vi;
             zi[r] -= c.re * vi + c.im * vr;
+            const double yr = yo[r].x, yi = yo[r].y, xr = xo[r].x, xi = xo[r].y;
+            sr += vr * yr + vi * yi;
+            si += vr * yi - vi * yr;
+            gr += vr * xr + vi * xi;
+            gi += vr * xi - vi * xr;
+          }
+          if (nb) {
+            sr = wave_sum(sr);
+            si = wave_sum(si);
+            gr = wave_sum(gr);
+            gi = wave_sum(gi);
+            if ((int)lane == i + j - a.i0) {
+              aar += sr;
+              aai += si;
+              agr += gr;
+              agi += gi;
+            }
           }
         }
       }
     }
-    // store w; the dots below use the stored (rounded) values
+    // store w; its norm from the stored (rounded) values
     double nn = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -500,68 +627,25 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
       V o;
       o.x = (R)zr[r];
       o.y = (R)zi[r];
-      zr[r] = o.x;
-      zi[r] = o.y;
       if (!a.geo.small || s < a.geo.D) {
         out[s] = o;
-        nn += zr[r] * zr[r] + zi[r] * zi[r];
-      } else {
-        zr[r] = zi[r] = 0.0;
+        const double wr = o.x, wi = o.y;
+        nn += wr * wr + wi * wi;
       }
     }
     acc_nn += wave_sum(nn);
-    // next step's window dots <y_i|w>, NW per round trip; y_k is in registers
-    for (int i = a.i0n; i <= a.k; i += NW) {
-      V q[NW][NR];
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        if (i + j < a.k) {
-          const V* yj = y_ptr<V>(a, i + j);
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const uint32_t s = base | eb | ((uint32_t)r << 6);
-            const bool ok = !a.geo.small || s < a.geo.D;
-            q[j][r] = ok ? yj[s] : V{(R)0, (R)0};
-          }
-        } else if (i + j == a.k) {
-#pragma unroll
-          for (int r = 0; r < NR; ++r) q[j][r] = yo[r];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        if (i + j <= a.k) {
-          double sr = 0.0, si = 0.0;
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const double yr = q[j][r].x, yi = q[j][r].y;
-            sr += yr * zr[r] + yi * zi[r];
-            si += yr * zi[r] - yi * zr[r];
-          }
-          sr = wave_sum(sr);
-          si = wave_sum(si);
-          if ((int)lane == i + j - a.i0n) {
-            acc_re += sr;
-            acc_im += si;
-          }
-        }
-      }
-    }
   }
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
-  if ((int)lane < nd) wacc[wv * kMaxScal + lane] = cplx_d{acc_re, acc_im};
-  if (lane == 0) wacc[wv * kMaxScal + nd] = cplx_d{acc_nn, 0.0};
+  if ((int)lane < nb) {
+    wacc[wv * kMaxScal + lane] = cplx_d{aar, aai};
+    wacc[wv * kMaxScal + nb + lane] = cplx_d{agr, agi};
+  }
+  if (lane == 0) wacc[wv * kMaxScal + 2 * nb] = cplx_d{acc_nn, 0.0};
   __syncthreads();
-  block_totals(wacc, nd + 1, tot);
-  // this block's row: the next step's dots, and its part of ||w||^2 for pass A(k+1)
-  for (int j = threadIdx.x; j < nd; j += blockDim.x) {
-    st_agent(&a.partials[(size_t)bl * kMaxScal + j].re, tot[j].re);
-    st_agent(&a.partials[(size_t)bl * kMaxScal + j].im, tot[j].im);
-  }
-  if (threadIdx.x == 0) {
-    st_agent(&a.partials[(size_t)bl * kMaxScal + kNormCol].re, tot[nd].re);
-    st_agent(&a.partials[(size_t)bl * kMaxScal + kNormCol].im, 0.0);
-  }
+  block_totals(wacc, 2 * nb + 1, tot);
+  // this block's row: the measurements, and its part of ||w||^2 for pass A(k+1)
+  for (int j = threadIdx.x; j < 2 * nb; j += blockDim.x) a.partials[(size_t)j * kPartialRows + bl] = tot[j];
+  if (threadIdx.x == 0) a.partials[(size_t)kNormCol * kPartialRows + bl] = cplx_d{tot[2 * nb].re, 0.0};
 }
 
 template <typename R, int RB>
@@ -919,7 +1003,7 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     la.geo = calls[j].geo;
     la.slot0 = calls[j].v_in;
     la.basis = wss[j]->basis;
-    la.ywin = wss[j]->ywin;
+    la.yk = wss[j]->yk;
     la.m = calls[j].m;
     la.t = calls[j].t;
     la.tol = calls[j].tol;
@@ -930,16 +1014,20 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
   Profiler* prof = profiler_for_call();
   const double vb = (double)c0.geo.D * sizeof(V) * n;
   hipError_t e;
+  // windows: all stored vectors (full re-orthogonalisation) or the last two;
+  // the last step only forms alpha
+  int i0p = 0;
   for (int k = 0; k < c0.m; ++k) {
     const bool last = (k == c0.m - 1);
     const int i0 = last ? k : (c0.reorth ? 0 : (k > 0 ? k - 1 : 0));
-    // window start of step k+1, whose dots pass B(k) forms
     const int i0n = (k + 1 == c0.m - 1) ? k + 1 : (c0.reorth ? 0 : k);
     for (int j = 0; j < n; ++j) {
       lb.job[j].k = k;
       lb.job[j].i0 = i0;
       lb.job[j].i0n = i0n;
+      lb.job[j].i0p = i0p;
     }
+    i0p = i0;
     const int nwin = k - i0 + 1;
     if (c0.pe) {
       // reduced basis: y = H v_k by the gather kernel, then pass A on the given y
@@ -948,7 +1036,7 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
         const char* xk = (k == 0) ? static_cast<const char*>(calls[j].v_in)
                                   : static_cast<const char*>(wss[j]->basis) +
                                         (size_t)(k - 1) * c0.geo.D * sizeof(V);
-        void* yk = static_cast<char*>(wss[j]->ywin) + (size_t)k * c0.geo.D * sizeof(V);
+        void* yk = wss[j]->yk;
         if ((e = launch_hv_pe_t<R>(lb.job[j].hv, *calls[j].pe, xk, yk, s)) != hipSuccess)
           return e;
       }
@@ -971,11 +1059,8 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     if (!last) {
       if (prof) profiler_start(prof, s);
       if ((e = launch_pass_r<R>(false, lb, n, s)) != hipSuccess) return e;
-      // y_k and the window are read for the update, v_{k+1} is written, and
-      // the stored H v vectors of the next window are read for its dots
-      // (y_k from registers)
-      const int nd = k - i0n + 1;
-      if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 2 + (nd > 0 ? nd - 1 : 0)) * vb);
+      // y_k and the window are read, v_{k+1} is written
+      if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 2) * vb);
     }
   }
   const uint32_t D = c0.geo.D;

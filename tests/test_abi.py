@@ -56,7 +56,7 @@ def test_workspace_and_state_sizes(lib):
     ws128 = lib.kg_workspace_bytes(ctypes.byref(h), ctypes.byref(k), _lib.KG_C128)
     ws64 = lib.kg_workspace_bytes(ctypes.byref(h), ctypes.byref(k), _lib.KG_C64)
     vb128, vb64 = 16 << 10, 8 << 10
-    assert ws128 - ws64 == 31 * (vb128 - vb64)         # 2 x (7 basis + 8 H v) + 1 costate
+    assert ws128 - ws64 == 17 * (vb128 - vb64)         # 2 x (7 basis + 1 H v) + 1 costate
     assert lib.kg_states_bytes(ctypes.byref(h), 100, 0, _lib.KG_C128) == 100 * vb128
     # checkpoints every 20: 4 checkpoints below the last segment + 2 x 20 buffer slots
     assert lib.kg_states_bytes(ctypes.byref(h), 100, 20, _lib.KG_C64) == 44 * vb64

@@ -131,3 +131,24 @@ def test_ascent_update_matches_oracle():
     assert np.abs(host(ud) - grape.ascent_update(u, g, 0.1)).max() <= 1e-15
     kg.grape_ascent_update(ud, torch.zeros(333, dtype=torch.float64, device="cuda"), 0.1)
     assert np.abs(host(ud) - grape.ascent_update(u, g, 0.1)).max() <= 1e-15
+
+
+
+@pytest.mark.parametrize("centred", [False, True])
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_side_stream_recomputation_is_bit_identical(centred, dtype, monkeypatch):
+    """Segment recomputation on the library's second stream gives exactly the
+    results of the same calls made on the caller's stream (KG_ONE_STREAM)."""
+    c = random_chain(12, 37, 0.05, 14, HC_SX, 1, 0.7, seed=21)
+    h, k = xxz_of(c), kg.Krylov(c.m)
+    u = torch.tensor(c.u, dtype=torch.float64, device="cuda")
+    args = (h, u, c.dt, k, dev_vec(c.psi0, dtype), dev_vec(c.target, dtype))
+    two = kg.grape_gradient(*args, ckpt_every=5, centred=centred)
+    g2, F2 = host(two.grad), float(host(two.F))
+    monkeypatch.setenv("KG_ONE_STREAM", "1")
+    one = kg.grape_gradient(*args, ckpt_every=5, centred=centred)
+    g1, F1 = host(one.grad), float(host(one.F))
+    monkeypatch.delenv("KG_ONE_STREAM")
+    stored = kg.grape_gradient(*args, ckpt_every=0, centred=centred)
+    assert np.array_equal(g1, g2) and F1 == F2
+    assert np.array_equal(host(stored.grad), g2)

@@ -140,3 +140,40 @@ def test_deterministic():
     a, _ = gpu_expv(L, 1.0, 0.5, HC_SX, 1, 0.3, psi, 0.05, 20, True, dtype=C64)
     b, _ = gpu_expv(L, 1.0, 0.5, HC_SX, 1, 0.3, psi, 0.05, 20, True, dtype=C64)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("u,t", [(1e12, 0.1), (0.3, 1e9)])
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_exponential_out_of_range_gives_nan(u, t, dtype):
+    """|t| ||T|| beyond the evaluated range ends the call with a NaN output
+    instead of an unbounded number of Taylor sub-steps."""
+    rng = np.random.default_rng(4)
+    psi = workloads.random_state(rng, 1 << 8)
+    out, _ = gpu_expv(8, 1.0, 0.5, HC_SX, 1, u, psi, t, 8, True, dtype=dtype)
+    assert np.isnan(out).all()
+
+
+def test_non_finite_amplitude_by_value_is_rejected():
+    psi = workloads.random_state(np.random.default_rng(4), 1 << 8)
+    with pytest.raises(kg.KgError):
+        gpu_expv(8, 1.0, 0.5, HC_SX, 1, float("inf"), psi, 0.1, 8, True)
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_non_finite_amplitude_on_the_device_gives_nan(dtype):
+    """A non-finite control amplitude in device memory (not checked on the
+    host) makes the fidelity NaN; the sweep still ends."""
+    rng = np.random.default_rng(5)
+    psi0 = dev_vec(workloads.random_state(rng, 1 << 8), dtype)
+    f = dev_vec(workloads.random_state(rng, 1 << 8), dtype)
+    u = torch.tensor([0.2, float("inf"), -0.1], dtype=torch.float64, device="cuda")
+    r = kg.grape_forward(kg.XXZ(8, 1.0, 0.5), u, 0.1, kg.Krylov(8), psi0, f)
+    assert np.isnan(float(host(r.F)))
+
+
+@pytest.mark.parametrize("dtype", [C64, C128])
+def test_non_finite_input_gives_nan(dtype):
+    psi = workloads.random_state(np.random.default_rng(6), 1 << 8)
+    psi[3] = np.nan
+    out, m_eff = gpu_expv(8, 1.0, 0.5, HC_SX, 1, 0.3, psi, 0.1, 8, True, dtype=dtype)
+    assert np.isnan(out).all() and m_eff == 1
