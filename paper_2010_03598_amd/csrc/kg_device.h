@@ -51,6 +51,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sums of four values over the 64 lanes of a wavefront at once; lane l
+// returns the total of v[l mod 4].  Two halving exchanges within quads (the
+// lane keeps the half its index bit selects and adds the partner's copy of
+// it), then sums over the other index bits.  The order of the additions is
+// fixed.  About a third of the instructions of four wave_sum calls.
+__device__ __forceinline__ double quad_sums(double v0, double v1, double v2, double v3) {
+  const int lane = threadIdx.x & 63;
+  // bit 1: lanes with the bit set keep values 2, 3
+  const bool b1 = (lane >> 1) & 1;
+  const double s0 = b1 ? v0 : v2, s1 = b1 ? v1 : v3;
+  double k0 = (b1 ? v2 : v0) + dpp_f64<0x4E>(s0);   // quad_perm [2,3,0,1]
+  double k1 = (b1 ? v3 : v1) + dpp_f64<0x4E>(s1);
+  // bit 0: lanes with the bit set keep the second of the two
+  const bool b0 = lane & 1;
+  double t = (b0 ? k1 : k0) + dpp_f64<0xB1>(b0 ? k0 : k1);   // quad_perm [1,0,3,2]
+  t += __shfl_xor(t, 4, 64);
+  t += dpp_f64<0x128>(t);   // row_ror:8, lane ^ 8 within rows of 16
+  t += __shfl_xor(t, 16, 64);
+  t += __shfl_xor(t, 32, 64);
+  return t;
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));

@@ -522,8 +522,23 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   const uint32_t eb = lane | (wv << (6 + RB));
   const int nb = (a.i0n <= a.k) ? a.k - a.i0 + 1 : 0;
   double acc_nn = 0.0;
-  // lane l: the measurements of window vector i0 + l
-  double aar = 0.0, aai = 0.0, agr = 0.0, agi = 0.0;
+  // this wavefront's measurements accumulate in its row of wacc: <v_i|y_k>
+  // in column i - i0, <v_i|v_k> in column nb + i - i0
+  cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
+  cplx_d* wrow = wacc + wv * kMaxScal;
+  for (int j = (int)lane; j < 2 * nb; j += 64) wrow[j] = cplx_d{0.0, 0.0};
+  // lanes 0..3 hold the totals of quad_sums: column w's re and im parts of the
+  // first dot, then of the second
+  const auto add_quad = [&](int w, double t) {
+    if (lane < 4u) {
+      cplx_d& d = wrow[(lane < 2u ? 0 : nb) + w];
+      if (lane & 1u) {
+        d.im += t;
+      } else {
+        d.re += t;
+      }
+    }
+  };
 
   const KState* st = a.st;
   const V* x = slot_ptr<V>(a, a.k);
@@ -564,14 +579,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
         si += vr * yi - vi * yr;
         gr += vr * vr + vi * vi;
       }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
-      gr = wave_sum(gr);
-      if ((int)lane == a.k - a.i0) {
-        aar += sr;
-        aai += si;
-        agr += gr;
-      }
+      add_quad(a.k - a.i0, quad_sums(sr, si, gr, 0.0));
     }
     // window vectors other than v_k, NW per round trip
     for (int i = a.i0; i < a.k; i += NW) {
@@ -604,18 +612,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
             gr += vr * xr + vi * xi;
             gi += vr * xi - vi * xr;
           }
-          if (nb) {
-            sr = wave_sum(sr);
-            si = wave_sum(si);
-            gr = wave_sum(gr);
-            gi = wave_sum(gi);
-            if ((int)lane == i + j - a.i0) {
-              aar += sr;
-              aai += si;
-              agr += gr;
-              agi += gi;
-            }
-          }
+          if (nb) add_quad(i + j - a.i0, quad_sums(sr, si, gr, gi));
         }
       }
     }
@@ -635,12 +632,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
     }
     acc_nn += wave_sum(nn);
   }
-  cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
-  if ((int)lane < nb) {
-    wacc[wv * kMaxScal + lane] = cplx_d{aar, aai};
-    wacc[wv * kMaxScal + nb + lane] = cplx_d{agr, agi};
-  }
-  if (lane == 0) wacc[wv * kMaxScal + 2 * nb] = cplx_d{acc_nn, 0.0};
+  if (lane == 0) wrow[2 * nb] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, 2 * nb + 1, tot);
   // this block's row: the measurements, and its part of ||w||^2 for pass A(k+1)
