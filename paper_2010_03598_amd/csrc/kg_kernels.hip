@@ -221,19 +221,50 @@ __device__ __forceinline__ const V* slot_ptr(const LzArgs& a, int i) {
 // read back: `fresh_alpha` replaces alpha[m_eff-1], `fresh_b0`/`fresh_s0`
 // beta0 and scale_0 (NaN: read from memory), and for step kf >= 1 the pair
 // (`off_kf`, `scale_kf`) replaces offd[kf] and scale[kf] (kf < 0: none).
-__device__ void finish_basis(const LzArgs& a, int m_eff, double fresh_alpha, double fresh_b0,
-                             double fresh_s0, int kf = -1, double off_kf = 0.0,
+// KState values that the finishing wavefront of pass A(k) reads, all written
+// by earlier launches.  The finishing wavefront loads them into LDS in one
+// batch (one memory round trip) before it uses any of them.
+struct FinScalars {
+  double alpha[kMaxM];
+  double offd[kMaxM];
+  double scale[kMaxM];
+  cplx_d coef[kMaxM];    // step k-1's projection coefficients (window order)
+  cplx_d gprev[kMaxM];   // the Gram column measured two steps back
+  cplx_d cdiag[kMaxM];
+  cplx_d csub[kMaxM];
+  double normT, beta0;
+};
+
+__device__ __forceinline__ void stage_fin(const LzArgs& a, FinScalars& fs) {
+  if (threadIdx.x >= 64) return;
+  const KState* st = a.st;
+  const int l = threadIdx.x;
+  fs.alpha[l] = st->alpha[l];
+  fs.offd[l] = st->offd[l];
+  fs.scale[l] = st->scale[l];
+  fs.coef[l] = st->coef[l];
+  fs.gprev[l] = st->gcol[a.k & 1][l];
+  fs.cdiag[l] = st->cdiag[l];
+  fs.csub[l] = st->csub[l];
+  if (l == 0) {
+    fs.normT = st->normT;
+    fs.beta0 = st->beta0;
+  }
+}
+
+__device__ void finish_basis(const LzArgs& a, const FinScalars& fs, int m_eff, double fresh_alpha,
+                             double fresh_b0, double fresh_s0, int kf = -1, double off_kf = 0.0,
                              double scale_kf = 0.0) {
   KState* st = a.st;
   const int i = threadIdx.x & 63;
   double ai = 0.0, lo = 0.0, hi = 0.0, sc = 0.0;
   if (i < m_eff) {
-    ai = (i == m_eff - 1 && !isnan(fresh_alpha)) ? fresh_alpha : st->alpha[i];
-    lo = (i > 0) ? (i == kf ? off_kf : st->offd[i]) : 0.0;
-    hi = (i + 1 < m_eff) ? (i + 1 == kf ? off_kf : st->offd[i + 1]) : 0.0;
-    sc = (i == 0 && !isnan(fresh_s0)) ? fresh_s0 : (i == kf ? scale_kf : st->scale[i]);
+    ai = (i == m_eff - 1 && !isnan(fresh_alpha)) ? fresh_alpha : fs.alpha[i];
+    lo = (i > 0) ? (i == kf ? off_kf : fs.offd[i]) : 0.0;
+    hi = (i + 1 < m_eff) ? (i + 1 == kf ? off_kf : fs.offd[i + 1]) : 0.0;
+    sc = (i == 0 && !isnan(fresh_s0)) ? fresh_s0 : (i == kf ? scale_kf : fs.scale[i]);
   }
-  const double b0 = isnan(fresh_b0) ? st->beta0 : fresh_b0;
+  const double b0 = isnan(fresh_b0) ? fs.beta0 : fresh_b0;
   double cr, ci;
   tri_exp_wave(ai, lo, hi, a.t, cr, ci);
   if (i < m_eff) st->dcomb[i] = cplx_d{b0 * cr * sc, b0 * ci * sc};
@@ -274,20 +305,21 @@ __device__ __forceinline__ void store_y(const Tile<R, RB>& T, typename VT<R>::T*
 // the products of two of them are dropped: the sums keep l in {j, p-1, p} and
 // j in {i-1, i}, which are all the terms of the three-term window.  In exact
 // arithmetic the dots are exact either way (G is then diagonal).
-__device__ cplx_d window_dots(const LzArgs& a, const cplx_d* tot, int nb, double ekk) {
+__device__ cplx_d window_dots(const LzArgs& a, const FinScalars& fs, const cplx_d* tot, int nb,
+                             double ekk) {
   KState* st = a.st;
   const int lane = threadIdx.x & 63;
   const int p = a.k - 1, ip = a.i0p;
   const int j = ip + lane;
   const bool has_pm = p - 1 >= ip;
-  // step p's coefficients (still in coef) and the stored scalars, read first
-  const cplx_d cp = st->coef[p - ip];
-  const cplx_d cpm = has_pm ? st->coef[p - 1 - ip] : cplx_d{0.0, 0.0};
-  const double sp = st->scale[p];
+  // step p's coefficients and the stored scalars
+  const cplx_d cp = fs.coef[p - ip];
+  const cplx_d cpm = has_pm ? fs.coef[p - 1 - ip] : cplx_d{0.0, 0.0};
+  const double sp = fs.scale[p];
   double er = 0.0, ei = 0.0;
   if (lane < nb) {
-    const cplx_d cj = st->coef[lane];
-    const double sj = st->scale[j];
+    const cplx_d cj = fs.coef[lane];
+    const double sj = fs.scale[j];
     const cplx_d gjp = tot[nb + lane];
     cplx_d gjm{0.0, 0.0};   // G_{j,p-1}
     if (has_pm) {
@@ -297,7 +329,7 @@ __device__ cplx_d window_dots(const LzArgs& a, const cplx_d* tot, int nb, double
       } else if (j == p - 1) {
         gjm = cplx_d{1.0 / (sj * sj), 0.0};
       } else {
-        gjm = st->gcol[(p - 1) & 1][j];
+        gjm = fs.gprev[j];   // gcol[(p - 1) & 1], staged
       }
     }
     er = sp * tot[lane].re - (cp.re * gjp.re - cp.im * gjp.im) -
@@ -324,15 +356,15 @@ __device__ cplx_d window_dots(const LzArgs& a, const cplx_d* tot, int nb, double
   const double emr = __shfl(er, min(max(src - 1, 0), 63), 64);
   const double emi = __shfl(ei, min(max(src - 1, 0), 63), 64);
   if (!want) return cplx_d{0.0, 0.0};
-  const cplx_d cd = st->cdiag[i];
+  const cplx_d cd = fs.cdiag[i];
   double dr = e1r + cd.re * e0r + cd.im * e0i;
   double di = e1i + cd.re * e0i - cd.im * e0r;
   if (i >= 1 && i - 1 >= ip) {
-    const cplx_d cs = st->csub[i];
+    const cplx_d cs = fs.csub[i];
     dr += cs.re * emr + cs.im * emi;
     di += cs.re * emi - cs.im * emr;
   }
-  const double si = st->scale[i];
+  const double si = fs.scale[i];
   return cplx_d{dr / si, di / si};
 }
 
@@ -350,6 +382,7 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   extern __shared__ unsigned char smem_raw[];
   V* lds = reinterpret_cast<V*>(smem_raw);
   __shared__ cplx_d tot[kMaxScal];
+  __shared__ FinScalars fs;
 
   const int nwin = a.k - a.i0 + 1;
   // pass B(k-1)'s window (two measured columns per vector), if step k has
@@ -360,7 +393,8 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
   const uint32_t eb = lane | (wv << (6 + RB));
-  double acc_re = 0.0, acc_im = 0.0, acc_nn = 0.0;   // this wavefront's totals
+  // this wavefront's totals: lane 0 Re<v_k|y>, lane 1 Im<v_k|y>, lane 2 ||v_k||^2
+  double acc = 0.0;
 
   const double u = control_value(a.hv);
   const V* x = slot_ptr<V>(a, a.k);
@@ -399,16 +433,12 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
       si += vr * yi - vi * yr;
       nn += vr * vr + vi * vi;
     }
-    acc_re += wave_sum(sr);
-    acc_im += wave_sum(si);
-    acc_nn += wave_sum(nn);
+    acc += quad_sums(sr, si, nn, 0.0);
   }
   __syncthreads();
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
-  if (lane == 0) {
-    wacc[wv * kMaxScal + ca] = cplx_d{acc_re, acc_im};
-    wacc[wv * kMaxScal + ca + 1] = cplx_d{acc_nn, 0.0};
-  }
+  // columns ca (re, im) and ca + 1 (re; im is 0) of this wavefront's row
+  if (lane < 4u) reinterpret_cast<double*>(&wacc[wv * kMaxScal + ca])[lane] = (lane < 3u) ? acc : 0.0;
   __syncthreads();
   block_totals(wacc, ns, tot, ca);
   // columns [0, ca) come from pass B(k-1); for k >= 1 its norm parts land in tot[ns]
@@ -418,6 +448,7 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   if (threadIdx.x >= 64) return;
 
   // ---- scalar update on wavefront 0 of the last block
+  if (a.k > 0) stage_fin(a, fs);
   KState* st = a.st;
   const int lane0 = threadIdx.x;
   const int k = a.k;
@@ -449,8 +480,8 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     // ||w|| of pass B(k-1): the off-diagonal entry of step k, or a breakdown
     // (an invariant Krylov space of dimension k)
     bk = sqrt(tot[ns].re);
-    if (bk <= a.tol * fmax(1.0, st->normT)) {
-      finish_basis(a, k, NAN, NAN, NAN);
+    if (bk <= a.tol * fmax(1.0, fs.normT)) {
+      finish_basis(a, fs, k, NAN, NAN, NAN);
       return;
     }
     sk = 1.0 / bk;
@@ -460,10 +491,10 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     }
   }
   // lane l: window index i0 + l (a window holds at most kMaxM <= 64 vectors)
-  const cplx_d d = (nb > 0) ? window_dots(a, tot, nb, tot[ns].re) : cplx_d{0.0, 0.0};
+  const cplx_d d = (nb > 0) ? window_dots(a, fs, tot, nb, tot[ns].re) : cplx_d{0.0, 0.0};
   if (lane0 < nwin) {
     const int i = a.i0 + lane0;
-    const double si = (i == k) ? sk : st->scale[i];
+    const double si = (i == k) ? sk : fs.scale[i];
     const double f = si * sk;
     const cplx_d t = (i == k) ? tot[ca] : d;
     const cplx_d c{t.re * f * si, t.im * f * si};
@@ -473,13 +504,13 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   }
   const double alpha = tot[ca].re * sk * sk;
   const double offk = (k == 0) ? 0.0 : bk;
-  const double prevT = (k == 0) ? 0.0 : st->normT;
+  const double prevT = (k == 0) ? 0.0 : fs.normT;
   const double normT = fmax(prevT, fabs(alpha) + offk);
   if (lane0 == 0) {
     st->alpha[k] = alpha;
     st->normT = normT;
   }
-  if (k == a.m - 1) finish_basis(a, a.m, alpha, b0, s0, k, bk, sk);
+  if (k == a.m - 1) finish_basis(a, fs, a.m, alpha, b0, s0, k, bk, sk);
 }
 
 template <typename R, int RB>
