@@ -127,6 +127,58 @@ def time_hv(kg, torch, L, dtype, reps=50):
             "launches": reps, "timing": "HIP graph of the launches, best of 3 replays"}
 
 
+def time_large(kg, torch, workloads, with_fp64=True):
+    """The large form: L=24 (D = 16,777,216), N=500 slices of dt=0.05, m=24
+    with full re-orthogonalisation, checkpoints every 22 slices.  One gradient
+    evaluation in complex64 + FP64 scalars (kernels sampled with HIP events)
+    and one in complex128, each after a two-slice warm-up through the same
+    workspace, and the error of the first against the second."""
+    c = workloads.large()
+    ckpt = workloads.LARGE_CKPT_EVERY
+    h = kg.XXZ(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    k = kg.Krylov(c.m, reorth=True)
+    res = {}
+    for dtype in (torch.complex64, torch.complex128)[:2 if with_fp64 else 1]:
+        u, psi0, f = gpu_inputs(c, dtype, torch)
+        ws = kg.Workspace(h, k, dtype)
+        kg.grape_gradient(h, u[:2].contiguous(), c.dt, k, psi0, f, workspace=ws)
+        states = kg.new_states(h, c.N, ckpt, dtype)
+        torch.cuda.synchronize()
+        prof = kg.profile(sample_every=16, max_launches=20000) \
+            if dtype == torch.complex64 else None
+        if prof:
+            prof.__enter__()
+        t0 = time.perf_counter()
+        r = kg.grape_gradient(h, u, c.dt, k, psi0, f, ckpt_every=ckpt, states=states, workspace=ws)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if prof:
+            prof.__exit__(None, None, None)
+        res[dtype] = (t1 - t0, float(r.F.cpu()), r.grad.cpu().numpy(),
+                      prof.result if prof else None)
+        log(f"large form: one gradient ({dtype}) in {t1 - t0:.2f} s")
+        del ws, states, r, u, psi0, f
+        torch.cuda.empty_cache()
+    sec64, F64, g64, prof = res[torch.complex64]
+    sec128, F128, g128, _ = res.get(torch.complex128, (float("nan"), F64, g64, None))
+    return {"study": "large form: one gradient evaluation",
+            "workload": f"open XXZ L={c.L} (D={c.D}), J=1, Delta={c.Delta}, Hc=Sx site 1, N={c.N}, "
+                        f"dt={c.dt}, m={c.m} full reorth, ckpt every {ckpt}, seed 4",
+            "c64": {"seconds": sec64, "gradient_evals_per_s": 1.0 / sec64,
+                    "precision": "complex64 vectors, FP64 scalars"},
+            "c128": {"seconds": sec128, "gradient_evals_per_s": 1.0 / sec128},
+            "mixed_vs_fp64_error": {
+                "F_rel": abs(F64 - F128) / abs(F128),
+                "grad_rel_l2": float(np.linalg.norm(g64 - g128) / np.linalg.norm(g128)),
+                "grad_rel_inf": float(np.abs(g64 - g128).max() / np.abs(g128).max()),
+                "F_fp64": F128},
+            "kernels_c64": {kk: {"launches_timed": v["launches"],
+                                 "avg_us": v["ms"] / v["launches"] * 1e3,
+                                 "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
+                            for kk, v in prof.items() if v["launches"]},
+            "peak_GBps": HBM_PEAK_GBS}
+
+
 def time_pe(kg, torch, workloads, steps=2, reps=20):
     """The reduced basis on the transport task at L=25, K=12 (2,600,612
     amplitudes), N=200 slices of dt=0.1, m=10: centred gradients (the paper's
@@ -434,6 +486,9 @@ def main():
                     help="run only the graph-timed H v at this L (complex64 and complex128)")
     ap.add_argument("--fig2b", type=str, default="", metavar="L:K,L:K,...",
                     help="run only the optimisation run-time study at these sizes, e.g. 8:4,10:4")
+    ap.add_argument("--large", action="store_true",
+                    help="time one gradient of the L=24, N=500 large form (c64 and c128) only")
+    ap.add_argument("--large-no-fp64", action="store_true", help="with --large: complex64 only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -470,6 +525,9 @@ def main():
         sizes = [tuple(int(v) for v in p.split(":")) for p in args.fig2b.split(",")]
         print(json.dumps({"study": "transfer-task optimisation run time (Fig. 2)",
                           "rows": fig2b(kg, torch, workloads, sizes)}), flush=True)
+        return
+    if args.large:
+        print(json.dumps(time_large(kg, torch, workloads, not args.large_no_fp64)), flush=True)
         return
     c = workloads.adjoint()
     ckpt = workloads.ADJOINT_CKPT_EVERY
