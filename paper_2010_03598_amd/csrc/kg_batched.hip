@@ -188,29 +188,36 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
 #pragma unroll
         for (int j = 0; j < 8; ++j)
           if (i + j < k) q[j] = bslot(c, in, i + j)[s];
+        // two window vectors' dots per wavefront sum: quad_sums leaves value v
+        // of {Re, Im of vector j, Re, Im of vector j+1} in lane v
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < 8; j += 2) {
           if (i + j < k) {
-            double sr = (double)q[j].x * yr + (double)q[j].y * yi;
-            double si = (double)q[j].x * yi - (double)q[j].y * yr;
-            sr = wave_sum(sr);
-            si = wave_sum(si);
+            const bool two = i + j + 1 < k;
+            const double s0 = (double)q[j].x * yr + (double)q[j].y * yi;
+            const double s1 = (double)q[j].x * yi - (double)q[j].y * yr;
+            const double s2 = two ? (double)q[j + 1].x * yr + (double)q[j + 1].y * yi : 0.0;
+            const double s3 = two ? (double)q[j + 1].x * yi - (double)q[j + 1].y * yr : 0.0;
+            const double t = quad_sums(s0, s1, s2, s3);
             if ((int)lane == i + j - i0) {
-              acc_re += sr;
-              acc_im += si;
+              acc_re += lane_value(t, 0);
+              acc_im += lane_value(t, 1);
+            }
+            if (two && (int)lane == i + j + 1 - i0) {
+              acc_re += lane_value(t, 2);
+              acc_im += lane_value(t, 3);
             }
           }
         }
       }
       {
         const double xr = T.xr[0], xi = T.xi[0];
-        double sr = wave_sum(xr * yr + xi * yi);
-        double si = wave_sum(xr * yi - xi * yr);
+        const double t = quad_sums(xr * yr + xi * yi, xr * yi - xi * yr, xr * xr + xi * xi, 0.0);
         if ((int)lane == k - i0) {
-          acc_re += sr;
-          acc_im += si;
+          acc_re += lane_value(t, 0);
+          acc_im += lane_value(t, 1);
         }
-        acc_nn += wave_sum(xr * xr + xi * xi);
+        acc_nn += lane_value(t, 2);
       }
     }
     __syncthreads();

@@ -73,6 +73,13 @@ __device__ __forceinline__ double quad_sums(double v0, double v1, double v2, dou
   return t;
 }
 
+// The value of lane l (a wavefront-uniform l), in every lane.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
