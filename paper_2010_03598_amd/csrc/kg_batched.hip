@@ -179,7 +179,7 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
     double acc_re = 0.0, acc_im = 0.0, acc_nn = 0.0;
     for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
       __syncthreads();
-      hv_tile<float, kBRB, true>(T, c.hv, c.geo, tile, x, lds, u, nullptr);
+      hv_tile<float, kBRB, true>(T, c.hv, c.geo, tile, x, lds, u);
       const uint32_t s = (tile << kBTB) | lane | (wv << 6);
       const double yr = T.yr[0], yi = T.yi[0];
       if (!last) c.ybuf[s] = V{T.yr[0], T.yi[0]};   // for pass B of this member

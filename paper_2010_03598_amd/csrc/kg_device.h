@@ -73,6 +73,34 @@ __device__ __forceinline__ double quad_sums(double v0, double v1, double v2, dou
   return t;
 }
 
+// p[s] when `ok`, else zero.  The load is always issued (at index 0 when not
+// `ok`, so it stays in bounds) and the value masked afterwards.
+template <typename V>
+__device__ __forceinline__ V ld_masked(const V* p, uint32_t s, bool ok) {
+  const V v = p[ok ? s : 0u];
+  return ok ? v : V{0, 0};
+}
+
+// The NR amplitudes p[s0 | r << 6] of a thread's slots in a tile.  `full`
+// (the whole tile lies inside the vector) must be the same for the whole
+// block: then the loads are plain and unconditional, so the compiler issues
+// them together; a per-lane bound test around each load makes it wait for
+// each one in turn.  Slots at or past D read as zero.
+template <typename V, int NR>
+__device__ __forceinline__ void load_slots(const V* p, uint32_t s0, bool full, uint32_t D,
+                                           V (&out)[NR]) {
+  if (full) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) out[r] = p[s0 | ((uint32_t)r << 6)];
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t s = s0 | ((uint32_t)r << 6);
+      out[r] = ld_masked(p, s, s < D);
+    }
+  }
+}
+
 // The value of lane l (a wavefront-uniform l), in every lane.
 __device__ __forceinline__ double lane_value(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -410,14 +438,11 @@ __device__ __forceinline__ void next_far(uint32_t& glb, R hJ, uint32_t& flip, R&
 // y = (H0 + u Hc) x on one tile (amplitudes base .. base + 2^TB - 1).  The
 // tile's amplitudes, the S^x partners and the first far partners are requested
 // in one round trip before anything waits (partners outside the tile with
-// coherent loads when kCoh: other workgroups of the launch wrote them); when `done_flag` is set (a finished
-// Krylov basis) the function returns false after issuing them, without
-// touching LDS, and the caller returns.
+// coherent loads when kCoh: other workgroups of the launch wrote them).
 template <typename R, int RB, bool kCoh = false>
-__device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const Geo& g,
+__device__ __forceinline__ void hv_tile(Tile<R, RB>& T, const HvArgs& a, const Geo& g,
                                         uint32_t tile, const typename VT<R>::T* __restrict__ x,
-                                        typename VT<R>::T* lds, double u,
-                                        const int32_t* done_flag) {
+                                        typename VT<R>::T* lds, double u) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
   constexpr int NS = FarSlots<R, RB>::n;
@@ -443,16 +468,7 @@ __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
 
   // ---- round trip 1: own amplitudes, S^x partners, first far partners
   V own[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const uint32_t s = base | eb | ((uint32_t)r << 6);
-    if (!g.small || s < g.D) {
-      own[r] = x[s];
-    } else {
-      own[r].x = (R)0;
-      own[r].y = (R)0;
-    }
-  }
+  load_slots<V, NR>(x, base | eb, !g.small, g.D, own);
   uint32_t f[NS];
   R cf[NS];
 #pragma unroll
@@ -472,7 +488,6 @@ __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
       for (int r = 0; r < NR; ++r) gq[j][r] = ld_partner<kCoh>(&x[(base | eb | ((uint32_t)r << 6)) ^ f[j]]);
     }
   }
-  if (done_flag && *done_flag) return false;
 
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -632,7 +647,7 @@ __device__ __forceinline__ bool hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
       T.yi[r] += cu * q[r].y;
     }
   }
-  return true;
+
 }
 
 __device__ __forceinline__ double control_value(const HvArgs& a) {

@@ -70,7 +70,7 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_hv(HvArgs a, Geo g, co
   for (uint32_t it = 0; it < iters; ++it) {
     const uint32_t tile = tile_of(g, it, blockIdx.x, gridDim.x);
     if (it) __syncthreads();
-    hv_tile<R, RB>(T, a, g, tile, v, lds, u, nullptr);
+    hv_tile<R, RB>(T, a, g, tile, v, lds, u);
     const uint32_t base = tile << g.TB;
 #pragma unroll
     for (int r = 0; r < (1 << RB); ++r) {
@@ -400,6 +400,9 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   const V* x = slot_ptr<V>(a, a.k);
   V* yk = reinterpret_cast<V*>(a.yk);
   const uint32_t iters = a.geo.ntiles / G;
+  // a finished basis (breakdown in an earlier step): the flag is read here
+  // and tested after the tile work, so its load waits on nothing
+  const bool finished = a.k > 0 && a.st->done != 0;
   Tile<R, RB> T;
   for (uint32_t it = 0; it < iters; ++it) {
     const uint32_t tile = tile_of(a.geo, it, bl, G);
@@ -410,18 +413,16 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
       for (int r = 0; r < NR; ++r) {
         const uint32_t s = base | eb | ((uint32_t)r << 6);
         const bool ok = s < a.geo.D;
-        const V xv = ok ? x[s] : V{(R)0, (R)0};
-        const V yy = ok ? yk[s] : V{(R)0, (R)0};
+        const V xv = ld_masked(x, s, ok);
+        const V yy = ld_masked(yk, s, ok);
         T.xr[r] = xv.x;
         T.xi[r] = xv.y;
         T.yr[r] = yy.x;
         T.yi[r] = yy.y;
       }
-      if (a.k > 0 && a.st->done) return;
     } else {
-      if (!hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u, a.k > 0 ? &a.st->done : nullptr))
-        return;
-      // y_k for pass B and for the window dots of later steps
+      hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u);
+      // y_k for pass B (of no use, but harmless, after a finished basis)
       if (a.k + 1 < a.m) store_y<R, RB>(T, yk, base, eb, a.geo);
     }
     // <v_k|y> and ||v_k||^2 from registers
@@ -435,6 +436,7 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     }
     acc += quad_sums(sr, si, nn, 0.0);
   }
+  if (finished) return;   // every block, before any barrier of the reduction
   __syncthreads();
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
   // columns ca (re, im) and ca + 1 (re; im is 0) of this wavefront's row
@@ -571,25 +573,36 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
     }
   };
 
-  const KState* st = a.st;
-  const V* x = slot_ptr<V>(a, a.k);
-  const V* yv = reinterpret_cast<const V*>(a.yk);
-  V* out = reinterpret_cast<V*>(a.basis) + (size_t)a.k * a.geo.D;
+  // pass B writes no scalar state and only v_{k+1}, so the scalars (uniform,
+  // through the scalar cache) and the vectors it reads cannot alias its stores
+  const KState* __restrict__ st = a.st;
+  const V* __restrict__ x = slot_ptr<V>(a, a.k);
+  const V* __restrict__ yv = reinterpret_cast<const V*>(a.yk);
+  V* __restrict__ out = reinterpret_cast<V*>(a.basis) + (size_t)a.k * a.geo.D;
   const uint32_t iters = a.geo.ntiles / G;
+  // the scale of v_k and the finished flag (a breakdown in an earlier step)
+  const double sk = st->scale[a.k];
+  const int32_t finished = st->done;
+  const bool full = !a.geo.small;
   // same block-to-tile map as pass A, so y is read back from the L2 that wrote it
   for (uint32_t it = 0; it < iters; ++it) {
     const uint32_t base = tile_of(a.geo, it, bl, G) << a.geo.TB;
     V yo[NR], xo[NR];
+    if (full) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const uint32_t s = base | eb | ((uint32_t)r << 6);
-      const bool ok = !a.geo.small || s < a.geo.D;
-      yo[r] = ok ? yv[s] : V{(R)0, (R)0};
-      xo[r] = ok ? x[s] : V{(R)0, (R)0};
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t s = base | eb | ((uint32_t)r << 6);
+        yo[r] = yv[s];
+        xo[r] = x[s];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t s = base | eb | ((uint32_t)r << 6);
+        yo[r] = ld_masked(yv, s, s < a.geo.D);
+        xo[r] = ld_masked(x, s, s < a.geo.D);
+      }
     }
-    // a finished basis (breakdown in an earlier step) leaves nothing to do
-    if (it == 0 && st->done) return;
-    const double sk = st->scale[a.k];
     double zr[NR], zi[NR];
     {
       const cplx_d c = st->coef[a.k - a.i0];
@@ -617,15 +630,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
       V q[NW][NR];
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        if (i + j < a.k) {
-          const V* vj = slot_ptr<V>(a, i + j);
-#pragma unroll
-          for (int r = 0; r < NR; ++r) {
-            const uint32_t s = base | eb | ((uint32_t)r << 6);
-            const bool ok = !a.geo.small || s < a.geo.D;
-            q[j][r] = ok ? vj[s] : V{(R)0, (R)0};
-          }
-        }
+        if (i + j < a.k) load_slots<V, NR>(slot_ptr<V>(a, i + j), base | eb, full, a.geo.D, q[j]);
       }
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
@@ -647,6 +652,8 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
         }
       }
     }
+    // a finished basis stores nothing (every block returns, before any barrier)
+    if (finished) return;
     // store w; its norm from the stored (rounded) values
     double nn = 0.0;
 #pragma unroll
@@ -727,7 +734,7 @@ __device__ __forceinline__ void combine_body(const CombJob& cj, uint32_t D, uint
 #pragma unroll
           for (int q = 0; q < kStreamUnroll; ++q) {
             const uint32_t s = s0 + q * stride;
-            v[jj][q] = (s < D) ? vj[s] : V{(R)0, (R)0};
+            v[jj][q] = ld_masked(vj, s, s < D);
           }
         }
       }
@@ -792,8 +799,8 @@ __global__ void __launch_bounds__(kStreamBlock)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const uint32_t s = base + e * T + tid;
-      a[e] = (s < D) ? f[s] : V{(R)0, (R)0};
-      b[e] = (s < D) ? psi[s] : V{(R)0, (R)0};
+      a[e] = ld_masked(f, s, s < D);
+      b[e] = ld_masked(psi, s, s < D);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -843,15 +850,15 @@ __global__ void __launch_bounds__(kStreamBlock)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const uint32_t s = base + e * T + tid;
-      l[e] = (s < D) ? lam[s] : V{(R)0, (R)0};
-      p[e] = (s < D) ? psi[s ^ flip] : V{(R)0, (R)0};
+      l[e] = ld_masked(lam, s, s < D);
+      p[e] = ld_masked(psi, s ^ flip, s < D);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const uint32_t s = base + e * T + tid;
       // (Hc psi)[s]: S^x flips one bit with amplitude 1/2; sum of S^z is diagonal
       // (in the reduced basis, of the orbit label's bit pattern)
-      const uint32_t pat = pe_reps ? ((s < D) ? pe_reps[s] : 0u) : s;
+      const uint32_t pat = pe_reps ? pe_reps[s < D ? s : 0u] : s;
       const double hc = (a.hc_kind == 0) ? 0.5 : 0.5 * a.sz_count - (double)__popc(pat & a.sz_mask);
       const double pr = hc * (double)p[e].x, pi = hc * (double)p[e].y;
       const double lr = l[e].x, li = l[e].y;
