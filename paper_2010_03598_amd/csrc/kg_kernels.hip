@@ -707,60 +707,81 @@ struct CombBatch {
   uint32_t grid;  // blocks per job
 };
 
+// One chunk of the combination: kStreamUnroll elements per thread, spaced `stride`
+// apart from s0.  FULL: every element exists, so no load or store is masked (kept
+// apart from the masked form so that the two never share a load's registers).
+template <typename R, bool FULL>
+__device__ __forceinline__ void combine_chunk(const typename VT<R>::T* __restrict__ slot0,
+                                              const typename VT<R>::T* __restrict__ basis,
+                                              typename VT<R>::T* __restrict__ out, const cplx_d* cs,
+                                              int me, uint32_t s0, uint32_t stride, uint32_t D) {
+  using V = typename VT<R>::T;
+  constexpr int NJ = 4;  // basis vectors per round trip
+  double ar[kStreamUnroll], ai[kStreamUnroll];
+#pragma unroll
+  for (int q = 0; q < kStreamUnroll; ++q) {
+    ar[q] = 0.0;
+    ai[q] = 0.0;
+  }
+  for (int j0 = 0; j0 < me; j0 += NJ) {
+    V v[NJ][kStreamUnroll];
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const int j = j0 + jj;
+      if (j < me) {
+        const V* vj = (j == 0) ? slot0 : basis + (size_t)(j - 1) * D;
+#pragma unroll
+        for (int q = 0; q < kStreamUnroll; ++q) {
+          const uint32_t s = s0 + q * stride;
+          v[jj][q] = FULL ? vj[s] : ld_masked(vj, s, s < D);
+        }
+      }
+    }
+#pragma unroll
+    for (int jj = 0; jj < NJ; ++jj) {
+      const int j = j0 + jj;
+      if (j < me) {
+        const cplx_d c = cs[j];
+#pragma unroll
+        for (int q = 0; q < kStreamUnroll; ++q) {
+          const double vr = v[jj][q].x, vi = v[jj][q].y;
+          ar[q] += c.re * vr - c.im * vi;
+          ai[q] += c.re * vi + c.im * vr;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kStreamUnroll; ++q) {
+    const uint32_t s = s0 + q * stride;
+    if (FULL || s < D) {
+      V o;
+      o.x = (R)ar[q];
+      o.y = (R)ai[q];
+      out[s] = o;
+    }
+  }
+}
+
 template <typename R>
 __device__ __forceinline__ void combine_body(const CombJob& cj, uint32_t D, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
-  constexpr int NJ = 4;  // basis vectors per round trip
+  __shared__ cplx_d cs[kMaxM];
   const KState* __restrict__ st = cj.st;
   const V* slot0 = reinterpret_cast<const V*>(cj.slot0);
   const V* basis = reinterpret_cast<const V*>(cj.basis);
   V* out = reinterpret_cast<V*>(cj.out);
   const int me = st->m_eff;
+  // the coefficients once per block, so that the streaming loop waits on vector loads only
+  if ((int)threadIdx.x < me) cs[threadIdx.x] = st->dcomb[threadIdx.x];
+  __syncthreads();
   const uint32_t stride = G * kStreamBlock;
-  for (uint32_t s0 = bl * kStreamBlock + threadIdx.x; s0 < D; s0 += stride * kStreamUnroll) {
-    double ar[kStreamUnroll], ai[kStreamUnroll];
-#pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {
-      ar[q] = 0.0;
-      ai[q] = 0.0;
-    }
-    for (int j0 = 0; j0 < me; j0 += NJ) {
-      V v[NJ][kStreamUnroll];
-#pragma unroll
-      for (int jj = 0; jj < NJ; ++jj) {
-        const int j = j0 + jj;
-        if (j < me) {
-          const V* vj = (j == 0) ? slot0 : basis + (size_t)(j - 1) * D;
-#pragma unroll
-          for (int q = 0; q < kStreamUnroll; ++q) {
-            const uint32_t s = s0 + q * stride;
-            v[jj][q] = ld_masked(vj, s, s < D);
-          }
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < NJ; ++jj) {
-        const int j = j0 + jj;
-        if (j < me) {
-          const cplx_d c = st->dcomb[j];
-#pragma unroll
-          for (int q = 0; q < kStreamUnroll; ++q) {
-            const double vr = v[jj][q].x, vi = v[jj][q].y;
-            ar[q] += c.re * vr - c.im * vi;
-            ai[q] += c.re * vi + c.im * vr;
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {
-      const uint32_t s = s0 + q * stride;
-      if (s < D) {
-        V o;
-        o.x = (R)ar[q];
-        o.y = (R)ai[q];
-        out[s] = o;
-      }
+  for (uint32_t c0 = bl * kStreamBlock; c0 < D; c0 += stride * kStreamUnroll) {
+    // block-uniform: every element of the block's chunk exists
+    if (c0 + (kStreamBlock - 1) + (kStreamUnroll - 1) * stride < D) {
+      combine_chunk<R, true>(slot0, basis, out, cs, me, c0 + threadIdx.x, stride, D);
+    } else {
+      combine_chunk<R, false>(slot0, basis, out, cs, me, c0 + threadIdx.x, stride, D);
     }
   }
   if (cj.m_eff_out && bl == 0 && threadIdx.x == 0) *cj.m_eff_out = me;
@@ -796,11 +817,19 @@ __global__ void __launch_bounds__(kStreamBlock)
   double sr = 0.0, si = 0.0;
   for (uint32_t base = 0; base < D; base += T * E) {
     V a[E], b[E];
+    if (base + E * T <= D) {  // the whole chunk exists (block-uniform test)
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const uint32_t s = base + e * T + tid;
-      a[e] = ld_masked(f, s, s < D);
-      b[e] = ld_masked(psi, s, s < D);
+      for (int e = 0; e < E; ++e) {
+        a[e] = f[base + e * T + tid];
+        b[e] = psi[base + e * T + tid];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const uint32_t s = base + e * T + tid;
+        a[e] = ld_masked(f, s, s < D);
+        b[e] = ld_masked(psi, s, s < D);
+      }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -847,11 +876,20 @@ __global__ void __launch_bounds__(kStreamBlock)
   double sr = 0.0, si = 0.0;
   for (uint32_t base = 0; base < D; base += T * E) {
     V l[E], p[E];
+    if (base + E * T <= D) {  // the whole chunk exists (block-uniform test)
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const uint32_t s = base + e * T + tid;
-      l[e] = ld_masked(lam, s, s < D);
-      p[e] = ld_masked(psi, s ^ flip, s < D);
+      for (int e = 0; e < E; ++e) {
+        const uint32_t s = base + e * T + tid;
+        l[e] = lam[s];
+        p[e] = psi[s ^ flip];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const uint32_t s = base + e * T + tid;
+        l[e] = ld_masked(lam, s, s < D);
+        p[e] = ld_masked(psi, s ^ flip, s < D);
+      }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
