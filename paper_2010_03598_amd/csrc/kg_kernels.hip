@@ -235,20 +235,48 @@ struct FinScalars {
   double normT, beta0;
 };
 
-__device__ __forceinline__ void stage_fin(const LzArgs& a, FinScalars& fs) {
-  if (threadIdx.x >= 64) return;
+// One lane's share of FinScalars, read from the state by every block before its
+// arrival so that the load latency overlaps the reduction; the scalars come from
+// earlier launches.
+// Plain doubles, assigned one by one, so that they stay in registers.
+struct FinRegs {
+  double alpha = 0.0, offd = 0.0, scale = 0.0, normT = 0.0, beta0 = 0.0;
+  double coef_re = 0.0, coef_im = 0.0, gprev_re = 0.0, gprev_im = 0.0;
+  double cdiag_re = 0.0, cdiag_im = 0.0, csub_re = 0.0, csub_im = 0.0;
+};
+
+__device__ __forceinline__ void load_fin(const LzArgs& a, FinRegs& r) {
   const KState* st = a.st;
+  const int l = threadIdx.x & 63;
+  r.alpha = st->alpha[l];
+  r.offd = st->offd[l];
+  r.scale = st->scale[l];
+  r.normT = st->normT;
+  r.beta0 = st->beta0;
+  r.coef_re = st->coef[l].re;
+  r.coef_im = st->coef[l].im;
+  r.gprev_re = st->gcol[a.k & 1][l].re;
+  r.gprev_im = st->gcol[a.k & 1][l].im;
+  r.cdiag_re = st->cdiag[l].re;
+  r.cdiag_im = st->cdiag[l].im;
+  r.csub_re = st->csub[l].re;
+  r.csub_im = st->csub[l].im;
+}
+
+// Wavefront 0 of the finishing block puts the fetched scalars in LDS.
+__device__ __forceinline__ void stage_fin(const FinRegs& r, FinScalars& fs) {
+  if (threadIdx.x >= 64) return;
   const int l = threadIdx.x;
-  fs.alpha[l] = st->alpha[l];
-  fs.offd[l] = st->offd[l];
-  fs.scale[l] = st->scale[l];
-  fs.coef[l] = st->coef[l];
-  fs.gprev[l] = st->gcol[a.k & 1][l];
-  fs.cdiag[l] = st->cdiag[l];
-  fs.csub[l] = st->csub[l];
+  fs.alpha[l] = r.alpha;
+  fs.offd[l] = r.offd;
+  fs.scale[l] = r.scale;
+  fs.coef[l] = cplx_d{r.coef_re, r.coef_im};
+  fs.gprev[l] = cplx_d{r.gprev_re, r.gprev_im};
+  fs.cdiag[l] = cplx_d{r.cdiag_re, r.cdiag_im};
+  fs.csub[l] = cplx_d{r.csub_re, r.csub_im};
   if (l == 0) {
-    fs.normT = st->normT;
-    fs.beta0 = st->beta0;
+    fs.normT = r.normT;
+    fs.beta0 = r.beta0;
   }
 }
 
@@ -437,6 +465,10 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     acc += quad_sums(sr, si, nn, 0.0);
   }
   if (finished) return;   // every block, before any barrier of the reduction
+  // the earlier steps' scalars for the finishing block, in flight during the
+  // block reduction and the partials store (wavefront 0, which arrives)
+  FinRegs fr;
+  if (a.k > 0 && wv == 0) load_fin(a, fr);
   __syncthreads();
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
   // columns ca (re, im) and ca + 1 (re; im is 0) of this wavefront's row
@@ -450,7 +482,7 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   if (threadIdx.x >= 64) return;
 
   // ---- scalar update on wavefront 0 of the last block
-  if (a.k > 0) stage_fin(a, fs);
+  if (a.k > 0) stage_fin(fr, fs);
   KState* st = a.st;
   const int lane0 = threadIdx.x;
   const int k = a.k;
