@@ -574,7 +574,44 @@ __global__ void __launch_bounds__(1024) k_pass_a_y(LzBatch B) {
 // and, when step k+1 has window dots, of <v_i|y_k> (columns [0, nb)) and
 // <v_i|v_k> (columns [nb, 2nb)) for i in the window: the operands are already
 // in registers for the update, and pass A(k+1) derives its dots from them.
-template <typename R, int RB>
+// Placement of a thread's NR amplitudes in pass B's tile.  Pass B couples no
+// neighbours, so any placement that covers the tile will do.  kBPairs (whole
+// tiles, complex64): amplitude r = 2p + h at base | wv << (6+RB) | p << 7 |
+// lane << 1 | h, so that every load and store moves two amplitudes (16 bytes).
+// kBSlots / kBMasked: pass A's slots base | lane | wv << (6+RB) | r << 6, the
+// masked form for a vector shorter than its tile.
+enum BMode { kBPairs = 0, kBSlots = 1, kBMasked = 2 };
+
+template <int MODE, int RB>
+__device__ __forceinline__ uint32_t bpos(uint32_t base, uint32_t lane, uint32_t wv, int r) {
+  if constexpr (MODE == kBPairs) {
+    return base | (wv << (6 + RB)) | ((uint32_t)(r >> 1) << 7) | (lane << 1) | (uint32_t)(r & 1);
+  } else {
+    return base | lane | (wv << (6 + RB)) | ((uint32_t)r << 6);
+  }
+}
+
+template <int MODE, int RB, typename V, int NR>
+__device__ __forceinline__ void bload(const V* __restrict__ p, uint32_t base, uint32_t lane, uint32_t wv,
+                                      uint32_t D, V (&o)[NR]) {
+  if constexpr (MODE == kBPairs) {
+    static_assert(sizeof(V) == 8 && NR % 2 == 0, "pairs of complex64 amplitudes");
+#pragma unroll
+    for (int q = 0; q < NR / 2; ++q) {
+      const float4 v = *reinterpret_cast<const float4*>(p + bpos<MODE, RB>(base, lane, wv, 2 * q));
+      o[2 * q] = V{v.x, v.y};
+      o[2 * q + 1] = V{v.z, v.w};
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t s = bpos<MODE, RB>(base, lane, wv, r);
+      o[r] = (MODE == kBSlots) ? p[s] : ld_masked(p, s, s < D);
+    }
+  }
+}
+
+template <typename R, int RB, int MODE>
 __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
@@ -584,7 +621,6 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
 
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
-  const uint32_t eb = lane | (wv << (6 + RB));
   const int nb = (a.i0n <= a.k) ? a.k - a.i0 + 1 : 0;
   double acc_nn = 0.0;
   // this wavefront's measurements accumulate in its row of wacc: <v_i|y_k>
@@ -615,26 +651,13 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   // the scale of v_k and the finished flag (a breakdown in an earlier step)
   const double sk = st->scale[a.k];
   const int32_t finished = st->done;
-  const bool full = !a.geo.small;
+  const uint32_t D = a.geo.D;
   // same block-to-tile map as pass A, so y is read back from the L2 that wrote it
   for (uint32_t it = 0; it < iters; ++it) {
     const uint32_t base = tile_of(a.geo, it, bl, G) << a.geo.TB;
     V yo[NR], xo[NR];
-    if (full) {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const uint32_t s = base | eb | ((uint32_t)r << 6);
-        yo[r] = yv[s];
-        xo[r] = x[s];
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const uint32_t s = base | eb | ((uint32_t)r << 6);
-        yo[r] = ld_masked(yv, s, s < a.geo.D);
-        xo[r] = ld_masked(x, s, s < a.geo.D);
-      }
-    }
+    bload<MODE, RB>(yv, base, lane, wv, D, yo);
+    bload<MODE, RB>(x, base, lane, wv, D, xo);
     double zr[NR], zi[NR];
     {
       const cplx_d c = st->coef[a.k - a.i0];
@@ -662,7 +685,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
       V q[NW][NR];
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        if (i + j < a.k) load_slots<V, NR>(slot_ptr<V>(a, i + j), base | eb, full, a.geo.D, q[j]);
+        if (i + j < a.k) bload<MODE, RB>(slot_ptr<V>(a, i + j), base, lane, wv, D, q[j]);
       }
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
@@ -688,16 +711,25 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
     if (finished) return;
     // store w; its norm from the stored (rounded) values
     double nn = 0.0;
+    if constexpr (MODE == kBPairs) {
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      const uint32_t s = base | eb | ((uint32_t)r << 6);
-      V o;
-      o.x = (R)zr[r];
-      o.y = (R)zi[r];
-      if (!a.geo.small || s < a.geo.D) {
-        out[s] = o;
-        const double wr = o.x, wi = o.y;
-        nn += wr * wr + wi * wi;
+      for (int q = 0; q < NR / 2; ++q) {
+        const float4 o{(float)zr[2 * q], (float)zi[2 * q], (float)zr[2 * q + 1], (float)zi[2 * q + 1]};
+        *reinterpret_cast<float4*>(out + bpos<MODE, RB>(base, lane, wv, 2 * q)) = o;
+        nn += (double)o.x * o.x + (double)o.y * o.y + (double)o.z * o.z + (double)o.w * o.w;
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t s = bpos<MODE, RB>(base, lane, wv, r);
+        V o;
+        o.x = (R)zr[r];
+        o.y = (R)zi[r];
+        if (MODE == kBSlots || s < D) {
+          out[s] = o;
+          const double wr = o.x, wi = o.y;
+          nn += wr * wr + wi * wi;
+        }
       }
     }
     acc_nn += wave_sum(nn);
@@ -710,13 +742,13 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   if (threadIdx.x == 0) a.partials[(size_t)kNormCol * kPartialRows + bl] = cplx_d{tot[2 * nb].re, 0.0};
 }
 
-template <typename R, int RB>
+template <typename R, int RB, int MODE>
 __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzBatch B) {
   const uint32_t G = B.job[0].geo.grid;
   if (blockIdx.x < G) {
-    pass_b_body<R, RB>(B.job[0], blockIdx.x, G);
+    pass_b_body<R, RB, MODE>(B.job[0], blockIdx.x, G);
   } else {
-    pass_b_body<R, RB>(B.job[1], blockIdx.x - G, G);
+    pass_b_body<R, RB, MODE>(B.job[1], blockIdx.x - G, G);
   }
 }
 
@@ -1072,7 +1104,22 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
     hipLaunchKernelGGL((k_pass_a<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
   } else {
     const size_t red = ((size_t)1 << g.WB) * kMaxScal * sizeof(cplx_d);
-    hipLaunchKernelGGL((k_pass_b<R, RB>), grid, block, red, s, lb);
+    // 16-byte pairs need whole tiles and 16-byte aligned vectors (the boundary
+    // requires the alignment; checked again here, since a misaligned pair is
+    // not an option)
+    bool pairs = sizeof(R) == 4 && RB >= 1 && !g.small;
+    for (int j = 0; j < njobs; ++j) {
+      const LzArgs& q = lb.job[j];
+      if (((uintptr_t)q.slot0 | (uintptr_t)q.basis | (uintptr_t)q.yk) % 16) pairs = false;
+    }
+    if (g.small) {
+      hipLaunchKernelGGL((k_pass_b<R, RB, kBMasked>), grid, block, red, s, lb);
+    } else if (pairs) {
+      hipLaunchKernelGGL((k_pass_b<R, RB, (sizeof(R) == 4 && RB >= 1) ? kBPairs : kBSlots>), grid, block,
+                         red, s, lb);
+    } else {
+      hipLaunchKernelGGL((k_pass_b<R, RB, kBSlots>), grid, block, red, s, lb);
+    }
   }
   return hipGetLastError();
 }
