@@ -495,7 +495,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the chain's "
-              "slices are sequential and this build has no multi-GPU path", file=sys.stderr)
+              "slices are sequential and the library has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch
