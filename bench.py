@@ -179,6 +179,66 @@ def time_large(kg, torch, workloads, with_fp64=True):
             "peak_GBps": HBM_PEAK_GBS}
 
 
+def time_variants(kg, torch, workloads, nodes=(2, 4), n_columns=4):
+    """The gradient variants and operator control on the adjoint workload
+    (L=20, N=400, m=20, checkpoints every 20, complex64 + FP64 scalars): one
+    evaluation each, after a warm-up evaluation with the same buffers, of the
+    zeroth-order, centred and first-order gradients, the quadrature gradient
+    with each node count, and the operator-control gradient on `n_columns`
+    random columns."""
+    c = workloads.adjoint()
+    ckpt = workloads.ADJOINT_CKPT_EVERY
+    dtype = torch.complex64
+    h = kg.XXZ(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    k = kg.Krylov(c.m, reorth=True)
+    u, psi0, f = gpu_inputs(c, dtype, torch)
+    ws = kg.Workspace(h, k, dtype, extended=True)
+    states = kg.new_states(h, c.N, ckpt, dtype)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    rows = {}
+    cases = [("zeroth_order", {}), ("centred", {"centred": True}),
+             ("first_order", {"first_order": True})]
+    cases += [(f"quadrature_{n}", {"nodes": n}) for n in nodes]
+    for name, kw in cases:
+        sec, r = timed(lambda: kg.grape_gradient(h, u, c.dt, k, psi0, f, ckpt_every=ckpt,
+                                                 states=states, workspace=ws, **kw))
+        rows[name] = {"seconds": sec, "gradient_evals_per_s": 1.0 / sec}
+        log(f"variants: {name} in {sec:.3f} s")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    cols = torch.randn((n_columns, h.D), dtype=dtype, device="cuda", generator=g)
+    cols /= torch.linalg.vector_norm(cols, dim=1, keepdim=True)
+    tgts = torch.roll(cols, 1, dims=0).contiguous()
+    cstates = torch.empty(0)
+
+    def columns():
+        nonlocal cstates
+        r = kg.grape_gradient_columns(h, u, c.dt, k, cols, tgts, ckpt_every=ckpt,
+                                      states=cstates if cstates.numel() else None, workspace=ws)
+        cstates = r.states
+        return r
+
+    sec, _ = timed(columns)
+    rows[f"columns_{n_columns}"] = {"seconds": sec, "gradient_evals_per_s": 1.0 / sec}
+    log(f"variants: {n_columns} columns in {sec:.3f} s")
+    base = rows["zeroth_order"]["seconds"]
+    for v in rows.values():
+        v["relative_to_zeroth_order"] = v["seconds"] / base
+    return {"study": "gradient variants and operator control, one evaluation each",
+            "workload": f"open XXZ L={c.L}, N={c.N}, dt={c.dt}, m={c.m} full reorth, "
+                        f"ckpt every {ckpt}; columns: {n_columns} random normalised columns, "
+                        "targets the same columns rolled by one, seed 11",
+            "precision": "complex64 vectors, FP64 scalars", "rows": rows}
+
+
 def time_pe(kg, torch, workloads, steps=2, reps=20):
     """The reduced basis on the transport task at L=25, K=12 (2,600,612
     amplitudes), N=200 slices of dt=0.1, m=10: centred gradients (the paper's
@@ -489,6 +549,8 @@ def main():
     ap.add_argument("--large", action="store_true",
                     help="time one gradient of the L=24, N=500 large form (c64 and c128) only")
     ap.add_argument("--large-no-fp64", action="store_true", help="with --large: complex64 only")
+    ap.add_argument("--variants", action="store_true",
+                    help="time only the gradient variants and operator control at L=20")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-MiB device buffer 5 times (calibrates the HBM byte "
                          "counters against a kernel of known traffic) and exit")
@@ -528,6 +590,9 @@ def main():
         return
     if args.large:
         print(json.dumps(time_large(kg, torch, workloads, not args.large_no_fp64)), flush=True)
+        return
+    if args.variants:
+        print(json.dumps(time_variants(kg, torch, workloads)), flush=True)
         return
     c = workloads.adjoint()
     ckpt = workloads.ADJOINT_CKPT_EVERY
