@@ -267,7 +267,10 @@ __device__ bool arrive_last(uint32_t* counter, uint32_t cnt) {
   return true;
 }
 
-constexpr uint32_t kReduceFlat = 512;  // largest grid reduced in one level
+// largest grid reduced in one level: one block summing 635 rows beat the
+// two levels by 1.7 % per reduced-basis gradient (635 tiles); at 1024 rows
+// the two levels were ahead
+constexpr uint32_t kReduceFlat = 768;
 constexpr uint32_t kGroup = 64;        // blocks per group of the two-level reduction
 
 // Deterministic grid-wide sum of `ns` complex FP64 values.  Every block
