@@ -341,9 +341,11 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
   const bool acc = col > 0;
   const uint32_t* pe_reps = a.pe ? a.pe->reps : nullptr;
   const void* lam = a.target;
-  // (the quadrature's node states use the second slot on the caller's stream)
-  const bool quad = Q && Q->n > 0;
-  const SideStream* side = (S.c > 0 && S.nseg > 2 && !quad) ? side_stream(a.stream) : nullptr;
+  // The quadrature's node states use both slots as well: psi to the node on
+  // the caller's stream (slot 0, like the costate), lambda to the node on the
+  // side stream (slot 1, like the recomputation), or both in paired launches
+  // without a side stream.
+  const SideStream* side = (S.c > 0 && S.nseg > 2) ? side_stream(a.stream) : nullptr;
   for (int q = S.nseg - 1; q >= 0; --q) {
     if (side) {
       // the recomputation of this segment's loop overwrites the buffer that the
@@ -364,7 +366,18 @@ kg_status backward_sweep(const SweepArgs& a, const States& S, const double* beta
         for (int q = 0; q < Q->n; ++q) {
           const KrylovCall ca = krylov_call(a, j, Q->s[q], S.at0(j - 1), a.ws.node_a);
           const KrylovCall cb = krylov_call(a, j, -(a.dt - Q->s[q]), lam, a.ws.node_b);
-          KG_HIP(launch_krylov_pair(ca, a.ws, cb, a.ws1, a.stream), "quadrature node states");
+          if (side) {
+            // lambda's node state starts after the costate that made lambda and
+            // the bracket that last read node_b; the bracket waits for it
+            KG_HIP(hipEventRecord(side->fork, a.stream), "quadrature fork");
+            KG_HIP(hipStreamWaitEvent(side->s, side->fork, 0), "quadrature fork");
+            KG_HIP(launch_krylov(ca, a.ws, a.stream), "quadrature node state");
+            KG_HIP(launch_krylov(cb, a.ws1, side->s), "quadrature node state");
+            KG_HIP(hipEventRecord(side->join, side->s), "quadrature join");
+            KG_HIP(hipStreamWaitEvent(a.stream, side->join, 0), "quadrature join");
+          } else {
+            KG_HIP(launch_krylov_pair(ca, a.ws, cb, a.ws1, a.stream), "quadrature node states");
+          }
           KG_HIP(launch_bracket(a.prec, hc, a.geo.D, a.ws.node_b, a.ws.node_a, Q->w[q], beta_dev,
                                 a.ws, grad_dev + (j - 1), a.stream, q > 0, 0.0, pe_reps),
                  "quadrature bracket");
