@@ -173,8 +173,12 @@ kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double 
  * states_valid = 1 reuses the states and beta of a preceding grape_forward
  * with the same arguments (no forward sweep); 0 runs the forward sweep first.
  * With ckpt_every > 0 the segments between checkpoints are recomputed; the
- * result is bit-identical to ckpt_every = 0.  F_dev, beta_dev as in
- * grape_forward.  Errors: KG_EINVAL, KG_EWORKSPACE, KG_EDEVICE. */
+ * result is bit-identical to ckpt_every = 0.  With more than two segments
+ * (N > 2 ckpt_every) the recomputation overwrites the segment buffers, so the
+ * call uses the states up: a further gradient call on the same buffer needs
+ * states_valid = 0 (every gradient variant below behaves the same way).
+ * F_dev, beta_dev as in grape_forward.  Errors: KG_EINVAL, KG_EWORKSPACE,
+ * KG_EDEVICE. */
 kg_status grape_gradient(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
                          const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
                          double* F_dev, double* beta_dev, double* grad_dev, void* states,

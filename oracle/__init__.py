@@ -21,9 +21,11 @@ exact     plain definitions the method approximates: dense propagators by
           (Eqs. B3-B5) by Daleckii-Krein divided differences and by Van Loan's
           block exponential, quadrature of the natural gradient (Eqs. B7-B8),
           and central finite differences.
+dimension the Krylov dimension of the batched form: the smallest m whose a-priori
+          error bound (Hochbruck-Lubich) meets a requested accuracy per slice.
 
 Every function is pinned by tests marked ``not gpu`` against closed forms,
 invariants, brute force and library routines (see tests/test_oracle_*.py).
 """
 
-from . import model, krylov, grape, exact  # noqa: F401
+from . import model, krylov, grape, exact, dimension  # noqa: F401

@@ -29,6 +29,15 @@ import torch
 from .api import XXZ, Krylov, Workspace, grape_forward, grape_gradient
 
 
+def states_used_up(N: int, ckpt_every: int) -> bool:
+    """True when a checkpointed gradient call leaves the state buffer changed: with
+    more than two segments the backward sweep recomputes the earlier segments
+    into the two segment buffers, where the forward sweep had left the last two."""
+    if ckpt_every <= 0:
+        return False
+    return (N + ckpt_every - 1) // ckpt_every > 2
+
+
 class GrapeFidelity(torch.autograd.Function):
     """F(u) = |<f| U_N(u_N) ... U_1(u_1) |psi0>|^2 with the adjoint gradient."""
 
@@ -44,19 +53,23 @@ class GrapeFidelity(torch.autograd.Function):
         ctx.nodes = nodes
         ctx.psi0, ctx.target, ctx.ws = psi0, target, ws
         ctx.states, ctx.beta = r.states, r.beta
+        ctx.states_intact = True
         ctx.save_for_backward(u)
         return r.F.clone()
 
     @staticmethod
     def backward(ctx, gF: torch.Tensor):
         (u,) = ctx.saved_tensors
+        # backward may run again on the same graph (retain_graph, gradcheck's
+        # reentrancy check): once a checkpointed sweep has used the states up,
+        # the next one runs the forward sweep again to restore them
         r = grape_gradient(ctx.h, u, ctx.dt, ctx.k, ctx.psi0, ctx.target,
-                           ckpt_every=ctx.ckpt_every, states=ctx.states, states_valid=True,
-                           beta=ctx.beta, workspace=ctx.ws, centred=ctx.centred,
-                           nodes=ctx.nodes)
+                           ckpt_every=ctx.ckpt_every, states=ctx.states,
+                           states_valid=ctx.states_intact, beta=ctx.beta, workspace=ctx.ws,
+                           centred=ctx.centred, nodes=ctx.nodes)
+        if states_used_up(u.numel(), ctx.ckpt_every):
+            ctx.states_intact = False
         grad_u = r.grad * gF.to(r.grad.dtype)
-        # the states stay with the graph: backward may run again on it
-        # (retain_graph, gradcheck's reentrancy check)
         return grad_u, None, None, None, None, None, None, None, None, None
 
 

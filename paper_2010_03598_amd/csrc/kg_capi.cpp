@@ -534,7 +534,7 @@ int hv_tile_bits(int L, int prec) {
   return (L <= 21) ? 10 : (L == 22 ? 11 : 12);
 }
 
-Geo make_geo(int L, int prec, int tile_bits_override) {
+Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap) {
   Geo g;
   memset(&g, 0, sizeof(g));
   g.L = L;
@@ -563,7 +563,7 @@ Geo make_geo(int L, int prec, int tile_bits_override) {
   g.WB = tb - 6 - g.RB;
   g.small = (L < g.TB) ? 1 : 0;
   g.ntiles = g.small ? 1u : (1u << (L - g.TB));
-  g.grid = (int)(g.ntiles < (uint32_t)kMaxGrid ? g.ntiles : (uint32_t)kMaxGrid);
+  g.grid = (int)(g.ntiles < (uint32_t)grid_cap ? g.ntiles : (uint32_t)grid_cap);
   return g;
 }
 
@@ -604,7 +604,7 @@ kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void
   KG_CHECK(check_vec(w, prec, "w"));
   if (overlap(v, w, vec_bytes(h->L, prec))) return fail(KG_EINVAL, "v and w overlap");
   const int tb_env = tile_override_from_env();
-  const Geo g = make_geo(h->L, prec, tb_env >= 6 ? tb_env : hv_tile_bits(h->L, prec));
+  const Geo g = make_geo(h->L, prec, tb_env >= 6 ? tb_env : hv_tile_bits(h->L, prec), kMaxGrid);
   const HvArgs a = make_hv(h, nullptr, u);
   Profiler* prof = profiler_for_launch();
   if (prof) profiler_start(prof, (hipStream_t)stream);
@@ -1120,24 +1120,30 @@ PeArgs pe_args(const kg_pe* pe) {
 
 // Lanczos tiles of the reduced basis: four amplitudes per thread, tiles of
 // 2^TB (TB = 8..12) amplitudes, the smallest TB that keeps the tile count at
-// or below 512; beyond kMaxGrid tiles the count is padded to a multiple of
-// the grid (the padded tail is masked like the ragged last tile).
+// or below kLzGrid.  Beyond that, each block takes `it` tiles and the grid is
+// the smallest multiple of 8 with grid * it >= the tile count; the count is
+// padded to grid * it (the padded tail is masked like the ragged last tile).
 Geo make_geo_pe(int L, uint64_t dim) {
   Geo g;
   memset(&g, 0, sizeof(g));
   g.L = L;
   g.D = (uint32_t)dim;
   int tb = 8;
-  while (tb < 12 && ((dim + ((uint64_t)1 << tb) - 1) >> tb) > 512) ++tb;
+  while (tb < 12 && ((dim + ((uint64_t)1 << tb) - 1) >> tb) > (uint64_t)kLzGrid) ++tb;
   uint64_t nt = (dim + ((uint64_t)1 << tb) - 1) >> tb;
   if (nt < 1) nt = 1;
-  if (nt > (uint64_t)kMaxGrid) nt = (nt + kMaxGrid - 1) / kMaxGrid * kMaxGrid;
+  uint64_t grid = nt;
+  if (nt > (uint64_t)kLzGrid) {
+    const uint64_t it = (nt + kLzGrid - 1) / kLzGrid;
+    grid = ((nt + it - 1) / it + 7) / 8 * 8;
+    nt = grid * it;
+  }
   g.TB = tb;
   g.RB = 2;
   g.WB = tb - 8;
   g.small = 1;
   g.ntiles = (uint32_t)nt;
-  g.grid = (int)(nt < (uint64_t)kMaxGrid ? nt : (uint64_t)kMaxGrid);
+  g.grid = (int)grid;
   return g;
 }
 

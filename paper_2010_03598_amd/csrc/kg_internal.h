@@ -14,18 +14,23 @@ constexpr int kMaxM = 64;          // largest Krylov dimension
 constexpr int kMaxScal = 2 * kMaxM + 3;
 constexpr int kMaxGrid = 2048;     // largest grid of the reducing kernels
 constexpr int kPartialRows = kMaxGrid + kMaxGrid / 64;  // block rows + group rows
+// largest grid of the Lanczos passes: every block of pass B reads the pass A
+// partials of all of them (32 bytes a row)
+constexpr int kLzGrid = 512;
 
 struct cplx_d {                    // complex FP64 with a fixed layout
   double re, im;
 };
 
 // Scalars of one Krylov call, resident in device memory.  offd[k] couples
-// v_{k-1} and v_k (offd[0] = 0); scale[k] = 1/||stored vector k||.
+// v_{k-1} and v_k (offd[0] = 0); scale[k] = 1/||stored vector k||.  Fields
+// that step k reads from step k-1 while step k's own values are written in
+// the same launch are kept twice, by the parity of the step.
 struct KState {
   double alpha[kMaxM];
   double offd[kMaxM + 1];
   double scale[kMaxM + 1];
-  cplx_d coef[kMaxM];     // projection coefficients of the current step (window order)
+  cplx_d coef[2][kMaxM];  // projection coefficients of step k (window order), at k & 1
   cplx_d dcomb[kMaxM];    // combination coefficients beta0 * c_j * scale_j
   // c^(i)_i and c^(i)_{i-1} of every step i (projection coefficients on the
   // stored vector itself and on its predecessor)
@@ -33,7 +38,7 @@ struct KState {
   cplx_d csub[kMaxM];
   cplx_d gcol[2][kMaxM];  // measured Gram columns <u_j|u_p>, by the parity of p
   double beta0;
-  double normT;           // max_{i<=k}(|alpha_i| + offd_i)
+  double normT[2];        // max_{i<=k}(|alpha_i| + offd_i), at k & 1
   int32_t m_eff;
   int32_t done;           // basis complete (normal end, breakdown or zero input)
   int32_t pad_[2];
@@ -42,6 +47,9 @@ struct KState {
   double fid;
   double g0;              // centred gradient: the bracket at the start of slice 1
   uint32_t counters[kMaxGrid / 64 + 4];  // arrivals in the running grid reduction
+  // totals of pass B(k-1)'s measurement columns (window order) and, after
+  // them, of its norm column, summed by helper wavefronts of pass A(k)
+  cplx_d colsum[kMaxScal];
 };
 
 struct HvArgs {            // the Hamiltonian H0 + u Hc of one chain
@@ -68,7 +76,9 @@ struct Geo {               // tiling of one state vector
   int32_t grid;            // blocks of the tiled kernels
 };
 
-Geo make_geo(int L, int prec, int tile_bits_override);
+// Tiling of a 2^L vector; grid_cap bounds the grid (kLzGrid for the Lanczos
+// passes, kMaxGrid for a standalone H v).
+Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap = kLzGrid);
 int stream_grid(uint32_t D);
 
 struct Workspace {         // carved from the caller's workspace

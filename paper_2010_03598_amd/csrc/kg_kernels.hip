@@ -20,21 +20,26 @@
 //
 // Lanczos (App. A, Algorithm 2 with the full re-orthonormalisation it
 // describes).  One basis step is two passes over the tile grid:
-//   pass A(k): x = stored v_k; y = H x, stored (the H v vector);
-//              h_i = <v_i|y> for the projection window, and <x|x>;
-//   pass B(k): w = s_k y - sum_i (h_i s_i) v_i, stored unnormalised as v_{k+1},
-//              and the blocks' parts of ||w||^2; a streaming pass over y and
-//              the window.  The norm is summed by the finishing block of
-//              pass A(k+1), which needs it first, so pass B ends without a
-//              grid-wide reduction of its own.
-// Storing y costs one vector write and read; recomputing it in pass B would
-// repeat the partner-tile reads of the far hopping bonds, which cost more.
-// Stored vectors are not rescaled: scale_k = 1/||stored_k|| lives in device
-// memory and is folded into the coefficients.  Each pass ends with a
-// deterministic two-level grid reduction in FP64 (fixed order, no
-// floating-point atomics); the last block to finish applies the scalar update
-// (alpha, beta, breakdown test) and, when the basis is complete, evaluates
-// exp(-itT) e_1 on one wavefront in FP64.  A final streaming pass forms
+//   pass A(k): x = stored v_k; y = H x, stored (the H v vector); each block
+//              writes its parts of <x|y> and ||x||^2 and ends (no grid-wide
+//              reduction); helper wavefronts sum the previous pass B's
+//              measurement columns over the grid;
+//   pass B(k): every block first runs the scalar update of step k on the same
+//              sums (breakdown test, window dots, projection coefficients),
+//              then w = s_k y - sum_i c_i v_i is stored unnormalised as
+//              v_{k+1}, with the blocks' parts of ||w||^2 and of the dots the
+//              next step derives its window dots from; a streaming pass over y
+//              and the window.
+// The scalar update costs each pass B block one memory round trip and a few
+// hundred FP64 instructions on one wavefront, instead of a serial tail in
+// which the last block of pass A waits for every partial and then computes
+// alone.  Storing y costs one vector write and read; recomputing it in pass B
+// would repeat the partner-tile reads of the far hopping bonds, which cost
+// more.  Stored vectors are not rescaled: scale_k = 1/||stored_k|| lives in
+// device memory and is folded into the coefficients.  Every sum is
+// deterministic in FP64 (fixed order, no floating-point atomics).  After the
+// last pass A, one wavefront runs the last step's update and evaluates
+// exp(-itT) e_1 in FP64, and a streaming pass forms
 // v_out = beta0 V^T exp(-itT) e_1 with FP64 accumulation.
 //
 // Blocks of the tiled kernels are mapped to tiles XCD by XCD: block b runs on
@@ -196,10 +201,14 @@ struct LzArgs {
 
 constexpr int kMaxJobs = 2;
 
-// Column of the partials table that carries pass B's norm parts to the next
-// pass A (pass A's own partials use columns 0..m <= kMaxM).
+// Columns of the partials table (column major, one row per block).  Pass B(k)
+// writes its measurements <u_j|y_k> in columns [0, nb) and <u_j|u_k> in
+// [nb, 2nb) (window order) and its part of ||w||^2 in kNormCol; pass A(k)
+// writes its parts of <v_k|y_k> and ||v_k||^2 in kACol and kACol + 1, which
+// no pass B writes.
+constexpr int kACol = 2 * kMaxM;
 constexpr int kNormCol = kMaxScal - 1;
-static_assert(kNormCol > 2 * kMaxM + 1, "norm column overlaps the window columns");
+static_assert(kACol + 2 == kNormCol, "partials columns");
 static_assert(kMaxM <= 64, "a window is held one vector per lane of a wavefront");
 
 // Independent Krylov calls of the same shape advanced by the same launches:
@@ -214,16 +223,8 @@ __device__ __forceinline__ const V* slot_ptr(const LzArgs& a, int i) {
                 : reinterpret_cast<const V*>(a.basis) + (size_t)(i - 1) * a.geo.D;
 }
 
-
-// Scalar tail of a basis: exp(-itT) e_1 on wavefront 0 of the finishing block
-// and the combination coefficients dcomb_j = beta0 c_j scale_j.  Values this
-// very kernel produced are passed in, since the wavefront's own stores are not
-// read back: `fresh_alpha` replaces alpha[m_eff-1], `fresh_b0`/`fresh_s0`
-// beta0 and scale_0 (NaN: read from memory), and for step kf >= 1 the pair
-// (`off_kf`, `scale_kf`) replaces offd[kf] and scale[kf] (kf < 0: none).
-// KState values that the finishing wavefront of pass A(k) reads, all written
-// by earlier launches.  The finishing wavefront loads them into LDS in one
-// batch (one memory round trip) before it uses any of them.
+// KState values of the earlier steps that the scalar update of step k reads,
+// staged in LDS by wavefront 0 (all written by earlier launches).
 struct FinScalars {
   double alpha[kMaxM];
   double offd[kMaxM];
@@ -235,10 +236,8 @@ struct FinScalars {
   double normT, beta0;
 };
 
-// One lane's share of FinScalars, read from the state by every block before its
-// arrival so that the load latency overlaps the reduction; the scalars come from
-// earlier launches.
-// Plain doubles, assigned one by one, so that they stay in registers.
+// One lane's share of FinScalars.  Plain doubles, assigned one by one, so that
+// they stay in registers while the loads are in flight.
 struct FinRegs {
   double alpha = 0.0, offd = 0.0, scale = 0.0, normT = 0.0, beta0 = 0.0;
   double coef_re = 0.0, coef_im = 0.0, gprev_re = 0.0, gprev_im = 0.0;
@@ -248,13 +247,14 @@ struct FinRegs {
 __device__ __forceinline__ void load_fin(const LzArgs& a, FinRegs& r) {
   const KState* st = a.st;
   const int l = threadIdx.x & 63;
+  const int pk = (a.k - 1) & 1;   // step k-1's copies
   r.alpha = st->alpha[l];
   r.offd = st->offd[l];
   r.scale = st->scale[l];
-  r.normT = st->normT;
+  r.normT = st->normT[pk];
   r.beta0 = st->beta0;
-  r.coef_re = st->coef[l].re;
-  r.coef_im = st->coef[l].im;
+  r.coef_re = st->coef[pk][l].re;
+  r.coef_im = st->coef[pk][l].im;
   r.gprev_re = st->gcol[a.k & 1][l].re;
   r.gprev_im = st->gcol[a.k & 1][l].im;
   r.cdiag_re = st->cdiag[l].re;
@@ -263,7 +263,7 @@ __device__ __forceinline__ void load_fin(const LzArgs& a, FinRegs& r) {
   r.csub_im = st->csub[l].im;
 }
 
-// Wavefront 0 of the finishing block puts the fetched scalars in LDS.
+// Wavefront 0 puts the fetched scalars in LDS.
 __device__ __forceinline__ void stage_fin(const FinRegs& r, FinScalars& fs) {
   if (threadIdx.x >= 64) return;
   const int l = threadIdx.x;
@@ -280,9 +280,38 @@ __device__ __forceinline__ void stage_fin(const FinRegs& r, FinScalars& fs) {
   }
 }
 
+// Column `col` of a partials table summed over rows [0, G): lane l adds rows l,
+// l + 64, ... in order (eight rows a lane in flight together), then a fixed
+// butterfly.  The same value in every lane.
+__device__ __forceinline__ cplx_d column_total(const cplx_d* col, uint32_t G) {
+  const uint32_t lane = threadIdx.x & 63u;
+  double re = 0.0, im = 0.0;
+  for (uint32_t b0 = 0; b0 < G; b0 += 8u * 64u) {
+    cplx_d v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = col[min(b0 + q * 64u + lane, G - 1u)];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool in = b0 + q * 64u + lane < G;
+      re += in ? v[q].re : 0.0;
+      im += in ? v[q].im : 0.0;
+    }
+  }
+  return cplx_d{wave_sum(re), wave_sum(im)};
+}
+
+// Scalar tail of a basis: exp(-itT) e_1 on wavefront 0 and the combination
+// coefficients beta0 c_j scale_j, into `dc` (LDS, nullable) and, with
+// `writer`, into the state with m_eff.  Before the last step (a breakdown
+// found in a pass B) the writer also sets the done flag, which stops the
+// later launches of the call.  The combination never sets it: its other
+// blocks read the flag to learn whether the basis ended before the last step.  `fresh_alpha`
+// replaces alpha[m_eff-1], `fresh_b0`/`fresh_s0` beta0 and scale_0 (NaN: from
+// fs), and for step kf >= 1 the pair (`off_kf`, `scale_kf`) replaces offd[kf]
+// and scale[kf] (kf < 0: none): values of the running step, not in fs.
 __device__ void finish_basis(const LzArgs& a, const FinScalars& fs, int m_eff, double fresh_alpha,
-                             double fresh_b0, double fresh_s0, int kf = -1, double off_kf = 0.0,
-                             double scale_kf = 0.0) {
+                             double fresh_b0, double fresh_s0, int kf, double off_kf,
+                             double scale_kf, cplx_d* dc, bool writer, int* me) {
   KState* st = a.st;
   const int i = threadIdx.x & 63;
   double ai = 0.0, lo = 0.0, hi = 0.0, sc = 0.0;
@@ -295,10 +324,17 @@ __device__ void finish_basis(const LzArgs& a, const FinScalars& fs, int m_eff, d
   const double b0 = isnan(fresh_b0) ? fs.beta0 : fresh_b0;
   double cr, ci;
   tri_exp_wave(ai, lo, hi, a.t, cr, ci);
-  if (i < m_eff) st->dcomb[i] = cplx_d{b0 * cr * sc, b0 * ci * sc};
+  if (i < m_eff) {
+    const cplx_d d{b0 * cr * sc, b0 * ci * sc};
+    if (dc) dc[i] = d;
+    if (writer) st->dcomb[i] = d;
+  }
   if (i == 0) {
-    st->m_eff = m_eff;
-    st->done = 1;
+    if (me) *me = m_eff;
+    if (writer) {
+      st->m_eff = m_eff;
+      if (a.k < a.m - 1) st->done = 1;
+    }
   }
 }
 
@@ -319,9 +355,9 @@ __device__ __forceinline__ void store_y(const Tile<R, RB>& T, typename VT<R>::T*
 }
 
 // The window dots of step k, d_i = <u_i|H u_k> for i in [i0, k), on wavefront
-// 0 of the finishing block of pass A(k) (lane l: i = i0 + l), without reading
-// a window vector.  u_i are the stored (unnormalised) vectors, s_i = 1/||u_i||
-// and c^(i) the projection coefficients of step i, so that pass B(i) stored
+// 0 (lane l: i = i0 + l), without reading a window vector.  u_i are the stored
+// (unnormalised) vectors, s_i = 1/||u_i|| and c^(i) the projection
+// coefficients of step i, so that pass B(i) stored
 //   u_{i+1} = s_i y_i - sum_j c^(i)_j u_j,   y_i = H u_i.
 // As H is Hermitian, d_i = <y_i|u_k> = (e_{i+1} + sum_j conj(c^(i)_j) e_j) / s_i
 // with e_j = <u_j|u_k>; and with p = k-1,
@@ -332,9 +368,10 @@ __device__ __forceinline__ void store_y(const Tile<R, RB>& T, typename VT<R>::T*
 // coefficients c^(i)_j (j < i-1) are of the order of the rounding error, so
 // the products of two of them are dropped: the sums keep l in {j, p-1, p} and
 // j in {i-1, i}, which are all the terms of the three-term window.  In exact
-// arithmetic the dots are exact either way (G is then diagonal).
+// arithmetic the dots are exact either way (G is then diagonal).  With
+// `writer` the measured column G_jp is kept in the state for step k+1.
 __device__ cplx_d window_dots(const LzArgs& a, const FinScalars& fs, const cplx_d* tot, int nb,
-                             double ekk) {
+                             double ekk, bool writer) {
   KState* st = a.st;
   const int lane = threadIdx.x & 63;
   const int p = a.k - 1, ip = a.i0p;
@@ -369,7 +406,7 @@ __device__ cplx_d window_dots(const LzArgs& a, const FinScalars& fs, const cplx_
       er -= cj.re * gjj;
       ei -= cj.im * gjj;
     }
-    st->gcol[p & 1][j] = gjp;   // for step k+1
+    if (writer) st->gcol[p & 1][j] = gjp;   // for step k+1
   } else if (lane == nb) {
     er = ekk;   // j = k
   }
@@ -396,11 +433,160 @@ __device__ cplx_d window_dots(const LzArgs& a, const FinScalars& fs, const cplx_
   return cplx_d{dr / si, di / si};
 }
 
-// Pass A(k): y = H v_k, stored as y_k (the last step keeps it in registers),
-// and this block's parts of <v_k|y> and ||v_k||^2 (columns 2nb and 2nb+1,
-// after pass B(k-1)'s 2nb measured columns in the same partials rows).  The
-// finishing block adds the columns of both passes and pass B's norm parts,
-// derives the window dots (window_dots) and runs the scalar update.
+// The reduced sums of step k into `tot` (LDS) and the earlier steps' scalars
+// into `fs` (LDS), in the layout the scalar update reads:
+//   tot[0, 2nb)   pass B(k-1)'s measurement totals (window dots of step k),
+//   tot[2nb]      <v_k|y_k>,  tot[2nb + 1] = (||v_k||^2, 0)  (k = 0 only),
+//   tot[2nb + 2]  ||w||^2 of pass B(k-1), the square of the next off-diagonal.
+// The totals of pass B(k-1)'s columns come from pass A(k)'s helper
+// wavefronts (KState::colsum); pass A(k)'s own columns are summed here over
+// its G rows.  Every wavefront issues its loads before it waits.  Ends with a
+// barrier; false (in every thread) when the basis ended in an earlier step.
+__device__ bool gather_step(const LzArgs& a, uint32_t G, int nb, FinScalars& fs, cplx_d* tot) {
+  __shared__ int ended;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wv = uniform_u32(threadIdx.x >> 6);
+  const uint32_t nw = blockDim.x >> 6;
+  const int k = a.k;
+  const int ca = 2 * nb, ns = ca + 2;
+  const KState* st = a.st;
+  // wavefronts that sum the A columns: kACol always, kACol + 1 at k = 0
+  const uint32_t wa0 = nw >= 2 ? 1u : 0u;
+  const uint32_t wa1 = nw >= 3 ? 2u : wa0;
+  if (wv == 0) {
+    FinRegs fr;
+    int d = 0;
+    cplx_d c0{0.0, 0.0}, c1{0.0, 0.0};
+    if (k > 0) {
+      d = st->done;
+      load_fin(a, fr);
+      c0 = st->colsum[lane];
+      c1 = st->colsum[lane + 64u];
+    }
+    if (wa0 == 0) {
+      const cplx_d t = column_total(a.partials + (size_t)kACol * kPartialRows, G);
+      if (lane == 0) tot[ca] = t;
+      if (k == 0) {
+        const cplx_d t1 = column_total(a.partials + (size_t)(kACol + 1) * kPartialRows, G);
+        if (lane == 0) tot[ca + 1] = t1;
+      }
+    }
+    if (k > 0) {
+      stage_fin(fr, fs);
+      const int nc = 2 * nb + 1;
+      if ((int)lane < nc) tot[(int)lane < ca ? (int)lane : ns] = c0;
+      if ((int)lane + 64 < nc) tot[(int)lane + 64 < ca ? (int)lane + 64 : ns] = c1;
+    }
+    if (lane == 0) ended = d;
+  } else {
+    if (wv == wa0) {
+      const cplx_d t = column_total(a.partials + (size_t)kACol * kPartialRows, G);
+      if (lane == 0) tot[ca] = t;
+    }
+    if (k == 0 && wv == wa1) {
+      const cplx_d t = column_total(a.partials + (size_t)(kACol + 1) * kPartialRows, G);
+      if (lane == 0) tot[ca + 1] = t;
+    }
+  }
+  __syncthreads();
+  return ended == 0;
+}
+
+// The scalar update of step k on wavefront 0, from gather_step's sums: the
+// breakdown test (or, at k = 0, the input norm), the window dots, the
+// projection coefficients c^(k) into `cf` (LDS, window order; nullable) and
+// 1/||v_k|| into *sk_out (nullable), alpha_k and the running ||T||.  Every block of a launch runs it on the same
+// values, so all of them get the same coefficients; the one with `writer`
+// keeps the scalars in the state for the later steps.  Returns true when the
+// basis goes on.  At the last step (k = m-1), or when it ends here (a zero or
+// non-finite input, a breakdown), it returns false after the combination
+// coefficients went to `dc`/*me (nullable) and, with `writer`, to the state.
+__device__ bool step_update(const LzArgs& a, const FinScalars& fs, const cplx_d* tot, int nb,
+                            bool writer, cplx_d* cf, double* sk_out, cplx_d* dc, int* me) {
+  KState* st = a.st;
+  const int lane = threadIdx.x;
+  const int k = a.k;
+  const int ca = 2 * nb, ns = ca + 2;
+  const int nwin = k - a.i0 + 1;
+  double sk, b0 = NAN, s0 = NAN, bk = 0.0;
+  if (k == 0) {
+    const double nn = tot[ca + 1].re;
+    if (!(nn > 0.0)) {
+      // a zero input gives a zero output; a non-finite one a NaN output
+      const bool zero = nn == 0.0;
+      if (lane == 0) {
+        if (writer) {
+          st->beta0 = zero ? 0.0 : NAN;
+          st->m_eff = zero ? 0 : 1;
+          st->dcomb[0] = cplx_d{NAN, NAN};
+          if (a.m > 1) st->done = 1;
+        }
+        if (dc) dc[0] = cplx_d{NAN, NAN};
+        if (me) *me = zero ? 0 : 1;
+      }
+      return false;
+    }
+    b0 = sqrt(nn);
+    sk = 1.0 / b0;
+    s0 = sk;
+    if (writer && lane == 0) {
+      st->beta0 = b0;
+      st->scale[0] = sk;
+      st->offd[0] = 0.0;
+      st->done = 0;
+    }
+  } else {
+    // ||w|| of pass B(k-1): the off-diagonal entry of step k, or a breakdown
+    // (an invariant Krylov space of dimension k)
+    bk = sqrt(tot[ns].re);
+    if (bk <= a.tol * fmax(1.0, fs.normT)) {
+      if (writer || dc) finish_basis(a, fs, k, NAN, NAN, NAN, -1, 0.0, 0.0, dc, writer, me);
+      return false;
+    }
+    sk = 1.0 / bk;
+    if (writer && lane == 0) {
+      st->offd[k] = bk;
+      st->scale[k] = sk;
+    }
+  }
+  // lane l: window index i0 + l (a window holds at most kMaxM <= 64 vectors)
+  const cplx_d d = (nb > 0) ? window_dots(a, fs, tot, nb, tot[ns].re, writer) : cplx_d{0.0, 0.0};
+  if (lane < nwin) {
+    const int i = a.i0 + lane;
+    const double si = (i == k) ? sk : fs.scale[i];
+    const double f = si * sk;
+    const cplx_d t = (i == k) ? tot[ca] : d;
+    const cplx_d c{t.re * f * si, t.im * f * si};
+    if (cf) cf[lane] = c;
+    if (writer) {
+      st->coef[k & 1][lane] = c;
+      if (i == k) st->cdiag[k] = c;
+      if (i == k - 1) st->csub[k] = c;
+    }
+  }
+  const double alpha = tot[ca].re * sk * sk;
+  const double offk = (k == 0) ? 0.0 : bk;
+  const double prevT = (k == 0) ? 0.0 : fs.normT;
+  const double normT = fmax(prevT, fabs(alpha) + offk);
+  if (writer && lane == 0) {
+    st->alpha[k] = alpha;
+    st->normT[k & 1] = normT;
+  }
+  if (k == a.m - 1) {
+    finish_basis(a, fs, a.m, alpha, b0, s0, k, bk, sk, dc, writer, me);
+    return false;
+  }
+  if (sk_out && lane == 0) *sk_out = sk;
+  return true;
+}
+
+// Pass A(k): y = H v_k, stored as y_k (not at the last step), and this block's
+// parts of <v_k|y> and ||v_k||^2 (row bl of the A columns).  No grid-wide
+// reduction: the scalar update of step k runs in the prologue of pass B(k)
+// (of the combination at the last step), in every block.  Helper wavefronts
+// (wavefront w of block b takes column b + w G) sum pass B(k-1)'s measurement
+// and norm columns over the grid into KState::colsum, so that pass B(k) reads
+// 2nb + 1 totals instead of the whole table.
 // kYIn: y_k was written by a separate H v kernel (the reduced basis); the pass
 // then loads it instead of forming it on the tile.
 template <typename R, int RB, bool kYIn = false>
@@ -409,17 +595,11 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   constexpr int NR = 1 << RB;
   extern __shared__ unsigned char smem_raw[];
   V* lds = reinterpret_cast<V*>(smem_raw);
-  __shared__ cplx_d tot[kMaxScal];
-  __shared__ FinScalars fs;
+  __shared__ double wsum[16][3];
 
-  const int nwin = a.k - a.i0 + 1;
-  // pass B(k-1)'s window (two measured columns per vector), if step k has
-  // window dots
-  const int nb = (a.k > 0 && a.i0 < a.k) ? a.k - a.i0p : 0;
-  const int ca = 2 * nb;
-  const int ns = ca + 2;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
+  const uint32_t nw = blockDim.x >> 6;
   const uint32_t eb = lane | (wv << (6 + RB));
   // this wavefront's totals: lane 0 Re<v_k|y>, lane 1 Im<v_k|y>, lane 2 ||v_k||^2
   double acc = 0.0;
@@ -450,7 +630,6 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
       }
     } else {
       hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u);
-      // y_k for pass B (of no use, but harmless, after a finished basis)
       if (a.k + 1 < a.m) store_y<R, RB>(T, yk, base, eb, a.geo);
     }
     // <v_k|y> and ||v_k||^2 from registers
@@ -464,87 +643,28 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
     }
     acc += quad_sums(sr, si, nn, 0.0);
   }
-  if (finished) return;   // every block, before any barrier of the reduction
-  // the earlier steps' scalars for the finishing block, in flight during the
-  // block reduction and the partials store (wavefront 0, which arrives)
-  FinRegs fr;
-  if (a.k > 0 && wv == 0) load_fin(a, fr);
+  if (finished) return;
+  // this block's row of the A columns, the wavefronts summed in order
+  if (lane < 3u) wsum[wv][lane] = acc;
   __syncthreads();
-  cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
-  // columns ca (re, im) and ca + 1 (re; im is 0) of this wavefront's row
-  if (lane < 4u) reinterpret_cast<double*>(&wacc[wv * kMaxScal + ca])[lane] = (lane < 3u) ? acc : 0.0;
-  __syncthreads();
-  block_totals(wacc, ns, tot, ca);
-  // columns [0, ca) come from pass B(k-1); for k >= 1 its norm parts land in tot[ns]
-  if (!grid_reduce(tot, ns, a.partials, a.st->counters, bl, G,
-                   a.k > 0 ? a.partials + (size_t)kNormCol * kPartialRows : nullptr, ca))
-    return;
-  if (threadIdx.x >= 64) return;
-
-  // ---- scalar update on wavefront 0 of the last block
-  if (a.k > 0) stage_fin(fr, fs);
-  KState* st = a.st;
-  const int lane0 = threadIdx.x;
-  const int k = a.k;
-  double sk, b0 = NAN, s0 = NAN, bk = 0.0;
-  if (k == 0) {
-    const double nn = tot[ca + 1].re;
-    if (!(nn > 0.0)) {
-      // a zero input gives a zero output; a non-finite one a NaN output
-      const bool zero = nn == 0.0;
-      if (lane0 == 0) {
-        st->beta0 = zero ? 0.0 : NAN;
-        st->normT = 0.0;
-        st->m_eff = zero ? 0 : 1;
-        st->dcomb[0] = cplx_d{NAN, NAN};
-        st->done = 1;
-      }
-      return;
+  if (threadIdx.x == 0) {
+    double sr = 0.0, si = 0.0, nn = 0.0;
+    for (uint32_t q = 0; q < nw; ++q) {
+      sr += wsum[q][0];
+      si += wsum[q][1];
+      nn += wsum[q][2];
     }
-    b0 = sqrt(nn);
-    sk = 1.0 / b0;
-    s0 = sk;
-    if (lane0 == 0) {
-      st->beta0 = b0;
-      st->scale[0] = sk;
-      st->offd[0] = 0.0;
-      st->done = 0;
-    }
-  } else {
-    // ||w|| of pass B(k-1): the off-diagonal entry of step k, or a breakdown
-    // (an invariant Krylov space of dimension k)
-    bk = sqrt(tot[ns].re);
-    if (bk <= a.tol * fmax(1.0, fs.normT)) {
-      finish_basis(a, fs, k, NAN, NAN, NAN);
-      return;
-    }
-    sk = 1.0 / bk;
-    if (lane0 == 0) {
-      st->offd[k] = bk;
-      st->scale[k] = sk;
-    }
+    a.partials[(size_t)kACol * kPartialRows + bl] = cplx_d{sr, si};
+    a.partials[(size_t)(kACol + 1) * kPartialRows + bl] = cplx_d{nn, 0.0};
   }
-  // lane l: window index i0 + l (a window holds at most kMaxM <= 64 vectors)
-  const cplx_d d = (nb > 0) ? window_dots(a, fs, tot, nb, tot[ns].re) : cplx_d{0.0, 0.0};
-  if (lane0 < nwin) {
-    const int i = a.i0 + lane0;
-    const double si = (i == k) ? sk : fs.scale[i];
-    const double f = si * sk;
-    const cplx_d t = (i == k) ? tot[ca] : d;
-    const cplx_d c{t.re * f * si, t.im * f * si};
-    st->coef[lane0] = c;
-    if (i == k) st->cdiag[k] = c;
-    if (i == k - 1) st->csub[k] = c;
+  // helpers: totals of pass B(k-1)'s columns (written by the previous launch)
+  const int nb = (a.k > 0 && a.i0 < a.k) ? a.k - a.i0p : 0;
+  const int nh = (a.k > 0) ? 2 * nb + 1 : 0;
+  for (int c = (int)bl + (int)(G * wv); c < nh; c += (int)(G * nw)) {
+    const int src = (c < 2 * nb) ? c : kNormCol;
+    const cplx_d t = column_total(a.partials + (size_t)src * kPartialRows, G);
+    if (lane == 0) a.st->colsum[c] = t;
   }
-  const double alpha = tot[ca].re * sk * sk;
-  const double offk = (k == 0) ? 0.0 : bk;
-  const double prevT = (k == 0) ? 0.0 : fs.normT;
-  const double normT = fmax(prevT, fabs(alpha) + offk);
-  if (lane0 == 0) {
-    st->alpha[k] = alpha;
-    st->normT = normT;
-  }
-  if (k == a.m - 1) finish_basis(a, fs, a.m, alpha, b0, s0, k, bk, sk);
 }
 
 template <typename R, int RB>
@@ -569,11 +689,13 @@ __global__ void __launch_bounds__(1024) k_pass_a_y(LzBatch B) {
   }
 }
 
-// Pass B(k): w = s_k y_k - sum_i c_i v_i over the window [i0, k] (FP64), stored
-// unnormalised as v_{k+1}, with this block's part of ||w||^2 (column kNormCol)
-// and, when step k+1 has window dots, of <v_i|y_k> (columns [0, nb)) and
-// <v_i|v_k> (columns [nb, 2nb)) for i in the window: the operands are already
-// in registers for the update, and pass A(k+1) derives its dots from them.
+// Pass B(k): the scalar update of step k in its prologue (every block, on the
+// same sums: gather_step, step_update), then w = s_k y_k - sum_i c_i v_i over
+// the window [i0, k] (FP64), stored unnormalised as v_{k+1}, with this block's
+// part of ||w||^2 (column kNormCol) and, when step k+1 has window dots, of
+// <v_i|y_k> (columns [0, nb)) and <v_i|v_k> (columns [nb, 2nb)) for i in the
+// window: the operands are already in registers for the update, and step k+1
+// derives its dots from them.
 // Placement of a thread's NR amplitudes in pass B's tile.  Pass B couples no
 // neighbours, so any placement that covers the tile will do.  kBPairs (whole
 // tiles, complex64): amplitude r = 2p + h at base | wv << (6+RB) | p << 7 |
@@ -618,9 +740,24 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   constexpr int NW = WinSlots<R, RB>::n;
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx_d tot[kMaxScal];
+  __shared__ FinScalars fs;
+  __shared__ cplx_d cf[kMaxM];
+  __shared__ double sk_s;
+  __shared__ int go;
 
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
+
+  // ---- the scalar update of step k (window dots of pass B(k-1)'s measurements)
+  const int nb_in = (a.k > 0 && a.i0 < a.k) ? a.k - a.i0p : 0;
+  if (!gather_step(a, G, nb_in, fs, tot)) return;
+  if (wv == 0) {
+    const bool cont = step_update(a, fs, tot, nb_in, bl == 0, cf, &sk_s, nullptr, nullptr);
+    if (lane == 0) go = cont ? 1 : 0;
+  }
+  __syncthreads();
+  if (!go) return;
+
   const int nb = (a.i0n <= a.k) ? a.k - a.i0 + 1 : 0;
   double acc_nn = 0.0;
   // this wavefront's measurements accumulate in its row of wacc: <v_i|y_k>
@@ -641,16 +778,13 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
     }
   };
 
-  // pass B writes no scalar state and only v_{k+1}, so the scalars (uniform,
-  // through the scalar cache) and the vectors it reads cannot alias its stores
-  const KState* __restrict__ st = a.st;
+  // the streaming part stores only v_{k+1}, so the vectors it reads cannot
+  // alias its stores
   const V* __restrict__ x = slot_ptr<V>(a, a.k);
   const V* __restrict__ yv = reinterpret_cast<const V*>(a.yk);
   V* __restrict__ out = reinterpret_cast<V*>(a.basis) + (size_t)a.k * a.geo.D;
   const uint32_t iters = a.geo.ntiles / G;
-  // the scale of v_k and the finished flag (a breakdown in an earlier step)
-  const double sk = st->scale[a.k];
-  const int32_t finished = st->done;
+  const double sk = sk_s;
   const uint32_t D = a.geo.D;
   // same block-to-tile map as pass A, so y is read back from the L2 that wrote it
   for (uint32_t it = 0; it < iters; ++it) {
@@ -660,7 +794,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
     bload<MODE, RB>(x, base, lane, wv, D, xo);
     double zr[NR], zi[NR];
     {
-      const cplx_d c = st->coef[a.k - a.i0];
+      const cplx_d c = cf[a.k - a.i0];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const double vr = xo[r].x, vi = xo[r].y;
@@ -690,7 +824,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
         if (i + j < a.k) {
-          const cplx_d c = st->coef[i + j - a.i0];
+          const cplx_d c = cf[i + j - a.i0];
           double sr = 0.0, si = 0.0, gr = 0.0, gi = 0.0;
 #pragma unroll
           for (int r = 0; r < NR; ++r) {
@@ -707,8 +841,6 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
         }
       }
     }
-    // a finished basis stores nothing (every block returns, before any barrier)
-    if (finished) return;
     // store w; its norm from the stored (rounded) values
     double nn = 0.0;
     if constexpr (MODE == kBPairs) {
@@ -737,7 +869,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   if (lane == 0) wrow[2 * nb] = cplx_d{acc_nn, 0.0};
   __syncthreads();
   block_totals(wacc, 2 * nb + 1, tot);
-  // this block's row: the measurements, and its part of ||w||^2 for pass A(k+1)
+  // this block's row: the measurements, and its part of ||w||^2 for step k+1
   for (int j = threadIdx.x; j < 2 * nb; j += blockDim.x) a.partials[(size_t)j * kPartialRows + bl] = tot[j];
   if (threadIdx.x == 0) a.partials[(size_t)kNormCol * kPartialRows + bl] = cplx_d{tot[2 * nb].re, 0.0};
 }
@@ -750,6 +882,18 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzBatch B) {
   } else {
     pass_b_body<R, RB, MODE>(B.job[1], blockIdx.x - G, G);
   }
+}
+
+// The scalar update of the last step (alpha_{m-1}, or a breakdown there) and
+// exp(-itT) e_1: one wavefront per Krylov call, writing the combination
+// coefficients and m_eff to the state for k_combine.  A basis that ended in
+// an earlier step (a breakdown found by a pass B) already has them.
+__global__ void __launch_bounds__(64) k_finish(LzBatch B) {
+  __shared__ cplx_d tot[kMaxScal];
+  __shared__ FinScalars fs;
+  const LzArgs& a = B.job[blockIdx.x];
+  if (gather_step(a, a.geo.grid, 0, fs, tot))
+    step_update(a, fs, tot, 0, true, nullptr, nullptr, nullptr, nullptr);
 }
 
 // ---------------------------------------------------------------------- streaming kernels
@@ -1053,7 +1197,8 @@ __global__ void k_init_state(KState* st) {
   if (i == 0) {
     st->done = 0;
     st->m_eff = 0;
-    st->normT = 0.0;
+    st->normT[0] = 0.0;
+    st->normT[1] = 0.0;
   }
 }
 
@@ -1210,6 +1355,9 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
       if (prof) profiler_stop(prof, s, kProfPassB, (nwin + 2) * vb);
     }
   }
+  // the last step's scalar update and the small exponential
+  hipLaunchKernelGGL(k_finish, dim3(n), dim3(64), 0, s, lb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint32_t D = c0.geo.D;
   cb.D = D;
   cb.grid = (uint32_t)stream_grid(D);

@@ -3,7 +3,8 @@ large to run the oracle inside a test (L=16 ascent, L=20 and L=24 chains).
 
 Calls only the oracle and the seeded input generators:
 
-    python tests/golden/make_golden.py [adjoint_short large_short ascent batched]
+    python tests/golden/make_golden.py [adjoint_short adjoint_full large_short large_ckpt
+                                        ascent batched batched_planned]
 
 Each JSON file records the workload, the oracle settings and the values.
 """
@@ -22,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
-from oracle import exact, grape, krylov, model  # noqa: E402
+from oracle import dimension, exact, grape, krylov, model  # noqa: E402
 
 
 def sample_rows(D, seed=123):
@@ -63,6 +64,19 @@ def gradient_case(name, c, exact_slices=()):
 def adjoint_short():
     c = workloads.adjoint(N=8)
     return gradient_case("adjoint L=20 with N=8 (seed 2)", c, exact_slices=range(8))
+
+
+def adjoint_full():
+    c = workloads.adjoint()
+    return gradient_case("adjoint L=20 with all N=400 slices (seed 2)", c)
+
+
+def large_ckpt():
+    c = workloads.large(N=LARGE_CKPT_N)
+    return gradient_case(f"large L=24 with N={LARGE_CKPT_N} (seed 4)", c)
+
+
+LARGE_CKPT_N = 6
 
 
 def large_short():
@@ -110,8 +124,32 @@ def batched():
             "chains": recs, "oracle_seconds": time.time() - t0}
 
 
-CASES = {"adjoint_short": adjoint_short, "large_short": large_short, "ascent": ascent,
-         "batched": batched}
+def batched_planned():
+    """The 64-chain batched workload (seed 3) with the Krylov dimension of each chain
+    chosen from the a-priori bound (oracle.dimension: accuracy 1e-8 per sweep, m in
+    8..24), the dimensions the batched form's planner must also choose."""
+    import dataclasses
+    recs = []
+    t0 = time.time()
+    for i, c in enumerate(workloads.batched()):
+        m = dimension.krylov_dimension(c.L, c.J, c.Delta, bin(c.hc_sites).count("1"),
+                                       float(np.max(np.abs(c.u))), c.dt, c.N)
+        c = dataclasses.replace(c, m=m)
+        ch = model.Chain(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+        r = grape.gradient(ch, c.u, c.psi0, c.target, c.dt, c.m, True,
+                           krylov.default_tol(krylov.EPS_C64))
+        recs.append({"chain": chain_record(c), "F": r.F, "beta": cplx(r.beta),
+                     "grad": r.grad.tolist()})
+        print(f"batched chain {i}: L={c.L} N={c.N} m={m} F={r.F:.6e}", flush=True)
+    return {"workload": "batched: 64 chains (seed 3), Krylov dimension per chain from "
+                        "oracle.dimension.krylov_dimension (tol 1e-8, m in 8..24)",
+            "reorth": True, "oracle": "grape.gradient per chain, complex64 breakdown tolerance",
+            "chains": recs, "oracle_seconds": time.time() - t0}
+
+
+CASES = {"adjoint_short": adjoint_short, "adjoint_full": adjoint_full,
+         "large_short": large_short, "large_ckpt": large_ckpt, "ascent": ascent,
+         "batched": batched, "batched_planned": batched_planned}
 
 
 if __name__ == "__main__":

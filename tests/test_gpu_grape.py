@@ -152,3 +152,27 @@ def test_side_stream_recomputation_is_bit_identical(centred, dtype, monkeypatch)
     stored = kg.grape_gradient(*args, ckpt_every=0, centred=centred)
     assert np.array_equal(g1, g2) and F1 == F2
     assert np.array_equal(host(stored.grad), g2)
+
+
+@pytest.mark.parametrize("dtype,tol", [(C128, 1e-10), (C64, 1e-4)])
+def test_gradient_at_largest_krylov_dimension(dtype, tol):
+    """m = 64 (the largest accepted) through the checkpointed sweeps: 4 segments, so
+    the recomputation runs beside the costate propagation."""
+    c = random_chain(10, 12, 0.2, 64, HC_SX, 1, 0.6, seed=64)
+    eps = krylov.EPS_C128 if dtype == C128 else krylov.EPS_C64
+    ref = run_oracle(c, vec_eps=eps)
+    r = run_gpu(c, dtype=dtype, ckpt_every=3)
+    assert max(errors(r, ref)) <= tol
+    stored = run_gpu(c, dtype=dtype, ckpt_every=0)
+    assert np.array_equal(host(stored.grad), host(r.grad))
+
+
+@pytest.mark.parametrize("L", [23, 24])
+def test_checkpointed_is_bit_identical_large(L):
+    """At the large vector sizes (complex64 tiles of 2^11 amplitudes from L = 23)
+    the checkpointed gradient with 3 segments equals the store-all one bit for bit."""
+    c = random_chain(L, 7, 0.05, 8, HC_SX, 1, 0.5, seed=L)
+    a = run_gpu(c, dtype=C64, ckpt_every=2)
+    b = run_gpu(c, dtype=C64, ckpt_every=0)
+    assert np.array_equal(host(a.grad), host(b.grad))
+    assert float(host(a.F)) == float(host(b.F))

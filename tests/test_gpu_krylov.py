@@ -50,6 +50,21 @@ def test_matches_oracle_c64(L, m):
     assert np.linalg.norm(out - ref) <= 1e-5
 
 
+@pytest.mark.parametrize("L,m", [(12, 32), (13, 40), (14, 48), (12, 64), (14, 64)])
+@pytest.mark.parametrize("reorth", [True, False])
+@pytest.mark.parametrize("dtype,tol", [(C128, 1e-12), (C64, 1e-5)])
+def test_large_krylov_dimension(L, m, reorth, dtype, tol):
+    """Krylov dimensions up to the largest the library accepts (64: a projection
+    window of one vector per lane, every column of the reduction rows in use)."""
+    rng = np.random.default_rng(L * 97 + m)
+    psi = workloads.random_state(rng, 1 << L)
+    eps = krylov.EPS_C128 if dtype == C128 else krylov.EPS_C64
+    ref, lz = oracle_expv(L, 1.0, 0.8, HC_SX, 1, -0.45, psi, 0.6, m, reorth, eps)
+    out, m_eff = gpu_expv(L, 1.0, 0.8, HC_SX, 1, -0.45, psi, 0.6, m, reorth, dtype=dtype)
+    assert m_eff == lz.m_eff == m
+    assert np.linalg.norm(out - ref) <= tol
+
+
 @pytest.mark.parametrize("tb", [6, 7, 8, 9, 10, 11, 12])
 @pytest.mark.parametrize("dtype", [C128, C64])
 def test_every_tiling(tb, dtype):

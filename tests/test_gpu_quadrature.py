@@ -104,4 +104,4 @@ def test_adjoint_chain_short_vs_oracle_exact_gradient():
     c = workloads.adjoint(N=8)
     r = gpu(c, 8)
     g = host(r.grad)[gold["exact_grad_slices"]]
-    assert rel_err(g, np.array(gold["exact_grad"])) <= 1e-9
+    assert rel_err(g, np.array(gold["exact_grad"])) <= 1e-10
