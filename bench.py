@@ -37,6 +37,10 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
 def gpu_inputs(c, dtype, torch):
     dev = torch.device("cuda:0")
     u = torch.tensor(c.u, dtype=torch.float64, device=dev)
@@ -127,25 +131,29 @@ def time_hv(kg, torch, L, dtype, reps=50):
             "launches": reps, "timing": "HIP graph of the launches, best of 3 replays"}
 
 
-def time_large(kg, torch, workloads, with_fp64=True):
+def time_large(kg, torch, workloads, with_fp64=True, plain=True):
     """The large form: L=24 (D = 16,777,216), N=500 slices of dt=0.05, m=24
     with full re-orthogonalisation, checkpoints every 22 slices.  One gradient
     evaluation in complex64 + FP64 scalars (kernels sampled with HIP events)
     and one in complex128, each after a two-slice warm-up through the same
-    workspace, and the error of the first against the second."""
+    workspace, and the error of the first against the second; with `plain`,
+    one more complex64 evaluation with plain Lanczos (three-term window, no
+    re-orthogonalisation) and its error against both."""
     c = workloads.large()
     ckpt = workloads.LARGE_CKPT_EVERY
     h = kg.XXZ(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
-    k = kg.Krylov(c.m, reorth=True)
     res = {}
-    for dtype in (torch.complex64, torch.complex128)[:2 if with_fp64 else 1]:
+    legs = [(torch.complex64, True)] + ([(torch.complex128, True)] if with_fp64 else [])
+    legs += [(torch.complex64, False)] if plain else []
+    for dtype, reorth in legs:
+        k = kg.Krylov(c.m, reorth=reorth)
         u, psi0, f = gpu_inputs(c, dtype, torch)
         ws = kg.Workspace(h, k, dtype)
         kg.grape_gradient(h, u[:2].contiguous(), c.dt, k, psi0, f, workspace=ws)
         states = kg.new_states(h, c.N, ckpt, dtype)
         torch.cuda.synchronize()
         prof = kg.profile(sample_every=16, max_launches=20000) \
-            if dtype == torch.complex64 else None
+            if (dtype == torch.complex64 and reorth) else None
         if prof:
             prof.__enter__()
         t0 = time.perf_counter()
@@ -154,13 +162,22 @@ def time_large(kg, torch, workloads, with_fp64=True):
         t1 = time.perf_counter()
         if prof:
             prof.__exit__(None, None, None)
-        res[dtype] = (t1 - t0, float(r.F.cpu()), r.grad.cpu().numpy(),
-                      prof.result if prof else None)
-        log(f"large form: one gradient ({dtype}) in {t1 - t0:.2f} s")
+        res[(dtype, reorth)] = (t1 - t0, float(r.F.cpu()), r.grad.cpu().numpy(),
+                                prof.result if prof else None)
+        log(f"large form: one gradient ({dtype}, reorth={reorth}) in {t1 - t0:.2f} s")
         del ws, states, r, u, psi0, f
         torch.cuda.empty_cache()
-    sec64, F64, g64, prof = res[torch.complex64]
-    sec128, F128, g128, _ = res.get(torch.complex128, (float("nan"), F64, g64, None))
+    sec64, F64, g64, prof = res[(torch.complex64, True)]
+    sec128, F128, g128, _ = res.get((torch.complex128, True), (float("nan"), F64, g64, None))
+    out_plain = None
+    if plain:
+        secp, Fp, gp, _ = res[(torch.complex64, False)]
+        out_plain = {"seconds": secp, "gradient_evals_per_s": 1.0 / secp,
+                     "precision": "complex64 vectors, FP64 scalars, plain Lanczos",
+                     "vs_full_reorth_c64": {"F_rel": abs(Fp - F64) / abs(F64),
+                                            "grad_rel_l2": rel_l2(gp, g64)},
+                     "vs_full_reorth_c128": {"F_rel": abs(Fp - F128) / abs(F128),
+                                             "grad_rel_l2": rel_l2(gp, g128)}}
     return {"study": "large form: one gradient evaluation",
             "workload": f"open XXZ L={c.L} (D={c.D}), J=1, Delta={c.Delta}, Hc=Sx site 1, N={c.N}, "
                         f"dt={c.dt}, m={c.m} full reorth, ckpt every {ckpt}, seed 4",
@@ -172,11 +189,28 @@ def time_large(kg, torch, workloads, with_fp64=True):
                 "grad_rel_l2": float(np.linalg.norm(g64 - g128) / np.linalg.norm(g128)),
                 "grad_rel_inf": float(np.abs(g64 - g128).max() / np.abs(g128).max()),
                 "F_fp64": F128},
+            "plain_lanczos_c64": out_plain,
             "kernels_c64": {kk: {"launches_timed": v["launches"],
                                  "avg_us": v["ms"] / v["launches"] * 1e3,
                                  "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
                             for kk, v in prof.items() if v["launches"]},
             "peak_GBps": HBM_PEAK_GBS}
+
+
+def m_eff_histogram(kg, torch, c, n_slices=40):
+    """Krylov dimensions reached by the forward propagations of the first
+    `n_slices` slices of the workload (complex64, the timed configuration),
+    through krylov_expv with its m_eff output: {m_eff: count}."""
+    h = kg.XXZ(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
+    k = kg.Krylov(c.m, reorth=True)
+    u, psi, _ = gpu_inputs(c, torch.complex64, torch)
+    ws = kg.Workspace(h, k, torch.complex64)
+    me = torch.zeros(n_slices, dtype=torch.int32, device="cuda")
+    for j in range(n_slices):
+        psi = kg.krylov_expv(h, float(c.u[j]), c.dt, psi, k, workspace=ws, m_eff=me[j:j + 1])
+    vals, counts = np.unique(me.cpu().numpy(), return_counts=True)
+    return {"sample": f"forward propagations of slices 1..{n_slices}, complex64",
+            "histogram": {str(int(v)): int(n) for v, n in zip(vals, counts)}}
 
 
 def time_variants(kg, torch, workloads, nodes=(2, 4), n_columns=4):
@@ -207,11 +241,34 @@ def time_variants(kg, torch, workloads, nodes=(2, 4), n_columns=4):
     cases = [("zeroth_order", {}), ("centred", {"centred": True}),
              ("first_order", {"first_order": True})]
     cases += [(f"quadrature_{n}", {"nodes": n}) for n in nodes]
+    kept = {}
     for name, kw in cases:
         sec, r = timed(lambda: kg.grape_gradient(h, u, c.dt, k, psi0, f, ckpt_every=ckpt,
                                                  states=states, workspace=ws, **kw))
         rows[name] = {"seconds": sec, "gradient_evals_per_s": 1.0 / sec}
+        if name == "zeroth_order":
+            kept["full"] = (float(r.F.cpu()), r.grad.cpu().numpy())
         log(f"variants: {name} in {sec:.3f} s")
+    # plain Lanczos (three-term window, no re-orthogonalisation): time and its
+    # difference from the fully re-orthogonalised gradient, both complex64, and
+    # from the complex128 one
+    kp = kg.Krylov(c.m, reorth=False)
+    sec, r = timed(lambda: kg.grape_gradient(h, u, c.dt, kp, psi0, f, ckpt_every=ckpt,
+                                             states=states, workspace=ws))
+    Fp, gp = float(r.F.cpu()), r.grad.cpu().numpy()
+    F0, g0 = kept["full"]
+    u128, psi128, f128 = gpu_inputs(c, torch.complex128, torch)
+    r128 = kg.grape_gradient(h, u128, c.dt, k, psi128, f128, ckpt_every=ckpt)
+    F128, g128 = float(r128.F.cpu()), r128.grad.cpu().numpy()
+    del r128
+    rows["zeroth_order_plain_lanczos"] = {
+        "seconds": sec, "gradient_evals_per_s": 1.0 / sec,
+        "vs_full_reorth_c64": {"F_rel": abs(Fp - F0) / abs(F0), "grad_rel_l2": rel_l2(gp, g0)},
+        "vs_full_reorth_c128": {"F_rel": abs(Fp - F128) / abs(F128),
+                                "grad_rel_l2": rel_l2(gp, g128)},
+        "full_reorth_c64_vs_c128": {"F_rel": abs(F0 - F128) / abs(F128),
+                                    "grad_rel_l2": rel_l2(g0, g128)}}
+    log(f"variants: plain Lanczos in {sec:.3f} s")
     g = torch.Generator(device="cuda")
     g.manual_seed(11)
     cols = torch.randn((n_columns, h.D), dtype=dtype, device="cuda", generator=g)
@@ -374,21 +431,21 @@ def fig2b(kg, torch, workloads, sizes, max_iter=300):
     return rows
 
 
-def batched_algorithmic_bytes(chains):
+def batched_algorithmic_bytes(chains, ms):
     """Bytes the batched launch must move (complex64 vectors, 8 B per amplitude):
     per chain, 2N-1 Krylov calls (store-all: no recomputation), each with pass A
     reading its window and writing y (no y in the last step), pass B reading y
     and the window and writing the next vector, and the combination reading
     m vectors and writing one; N brackets and the overlap read two vectors."""
     total = 0
-    for c in chains:
+    for c, m in zip(chains, ms):
         V = 8 << c.h.L
         per_call = 0
-        for k in range(c.m):
-            last = k == c.m - 1
+        for k in range(m):
+            last = k == m - 1
             nw = 1 if last else (k + 1 if c.reorth else min(k + 1, 2))
             per_call += (nw + (0 if last else 1)) + (0 if last else nw + 2)
-        per_call += c.m + 1
+        per_call += m + 1
         total += V * ((2 * c.N - 1) * per_call + 2 * c.N + 2)
     return total
 
@@ -412,10 +469,10 @@ def time_batched(kg, torch, workloads, steps=3, fp64=True):
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     b.check_status()
-    nbytes = batched_algorithmic_bytes(chains)
+    nbytes = batched_algorithmic_bytes(chains, b.m)
     out = {"chains": len(chains), "value": len(chains) / sec, "unit": "chain gradient evals/s",
            "ms_per_launch": sec * 1e3, "launches": steps, "team_cap": info["best_cap"],
-           "m": sorted({c.m for c in chains}), "element_slices": int(sum(c.N << c.h.L for c in chains)),
+           "m": sorted(set(b.m)), "m_per_chain": list(b.m), "element_slices": int(sum(c.N << c.h.L for c in chains)),
            "algorithmic_GB_per_launch": nbytes / 1e9,
            "algorithmic_GBps": nbytes / sec / 1e9,
            "frac_of_peak": nbytes / sec / 1e9 / HBM_PEAK_GBS,
@@ -428,7 +485,7 @@ def time_batched(kg, torch, workloads, steps=3, fp64=True):
         t0 = time.perf_counter()
         res = []
         for i, c in enumerate(chains):
-            r = kg.grape_gradient(c.h, c.u.to("cuda"), c.dt, kg.Krylov(c.m),
+            r = kg.grape_gradient(c.h, c.u.to("cuda"), c.dt, kg.Krylov(b.m[i]),
                                   c.psi0.to(torch.complex128).to("cuda"),
                                   c.target.to(torch.complex128).to("cuda"))
             res.append(r)
@@ -533,7 +590,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--fp64-warmup", type=int, default=1)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the L=24, N=500 large-form leg of the default run")
     ap.add_argument("--profile-every", type=int, default=64,
                     help="time every n-th Krylov call's kernels with HIP events (0: off)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -602,7 +662,7 @@ def main():
                                            args.warmup, args.profile_every)
     if args.fp64_steps > 0:
         sec128, F128, g128, _ = time_gradients(kg, torch, c, torch.complex128, ckpt,
-                                               args.fp64_steps, 0, 0)
+                                               args.fp64_steps, args.fp64_warmup, 0)
     else:
         sec128, F128, g128 = float("nan"), F64, g64
     errF = abs(F64 - F128) / abs(F128)
@@ -638,6 +698,8 @@ def main():
     pe = None if args.no_pe else time_pe(kg, torch, workloads)
     if pe:
         log(f"reduced basis: {pe['value']:.2f} gradient evals/s")
+    large = None if args.no_large else time_large(kg, torch, workloads)
+    meff = m_eff_histogram(kg, torch, c)
     cpu = None if args.no_cpu else cpu_baseline(c, args.cpu_budget)
 
     out = {
@@ -660,7 +722,7 @@ def main():
                    "L": c.L, "N": c.N, "m": c.m, "dt": c.dt, "ckpt_every": ckpt,
                    "precision": "complex64 vectors, FP64 scalars", "parallelism": "1 GPU"},
         "fp64": {"value": 1.0 / sec128, "unit": "gradient evals/s", "ms_per_step": sec128 * 1e3,
-                 "steps": args.fp64_steps},
+                 "steps": args.fp64_steps, "warmup": args.fp64_warmup},
         "mixed_vs_fp64_error": {"F_rel": errF, "grad_rel_l2": errg, "grad_rel_inf": errg_inf,
                                 "F_fp64": F128},
         "hv": {"L20_c64": hv20, "L24_c64": hv24, "L24_c128": hv24_128,
@@ -678,8 +740,10 @@ def main():
                      "step_achieved": step_bytes / sec64 / 1e9,
                      "step_frac": step_bytes / sec64 / 1e9 / HBM_PEAK_GBS},
         "kernels": classes,
+        "m_eff": meff,
         "batched": bat,
         "reduced_basis": pe,
+        "large": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

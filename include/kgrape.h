@@ -409,6 +409,60 @@ typedef struct kg_chain {
 /* Scratch bytes of one chain of the batched form. 0 for invalid arguments. */
 size_t kg_batched_chain_ws_bytes(int32_t L, int32_t m, int32_t team_size);
 
+/* Sizes of the packed buffers of a planned batch. */
+typedef struct kg_batch_plan {
+  int64_t u_len;        /* doubles of u_all and grad_all */
+  int64_t vec_len;      /* complex64 amplitudes of psi0_all and target_all */
+  int64_t states_len;   /* complex64 amplitudes of states_all */
+  uint64_t ws_bytes;    /* bytes of the workspace */
+  int32_t blocks_used;  /* workgroups covered by the teams (<= n_blocks) */
+  int32_t pad_;
+} kg_batch_plan;
+
+/* Host-only planning of a batch (no device call).  On input each chains[i]
+ * holds h, N, dt, reorth and breakdown_tol, and m (0: choose it) and, with
+ * keep_teams = 1, team_size.  The call fills in:
+ *   m           where it was 0: the smallest m in [m_min, m_max] for which the
+ *               a-priori error bound of the Lanczos approximation of
+ *               exp(-i dt H) v (Hochbruck and Lubich, SIAM J. Numer. Anal. 34
+ *               (1997), Theorem 2, for a skew-Hermitian argument), with the
+ *               spectral radius of H0 + u Hc bounded by Gershgorin's theorem
+ *               for |u| <= umax[i], is at most tol / N (m_max if none is).
+ *               The paper leaves the dimension to the user and points to
+ *               a-posteriori estimates for the choice (App. A);
+ *   team_size   with keep_teams = 0: one workgroup per chain, then the team of
+ *               the chain with the largest estimated time (2N(m^2 + 3m) 2^L
+ *               vector passes over its team size, the lowest index on ties) is
+ *               doubled while it stays within min(max_team, 2^L / 1024) and the
+ *               grid of n_blocks workgroups;
+ *   team_first, off_u, off_vec, off_states, off_ws
+ *               the chains packed one after the other in order (workspace
+ *               offsets 256-byte aligned);
+ * and *plan with the buffer sizes grape_gradient_batched then needs.  umax may
+ * be NULL when no m is 0.  Errors: KG_EINVAL. */
+kg_status kg_batched_plan(kg_chain* chains, int32_t n_chains, const double* umax, int32_t n_blocks,
+                          int32_t max_team, int32_t keep_teams, double tol, int32_t m_min,
+                          int32_t m_max, kg_batch_plan* plan);
+
+/* Autotuner of the team shapes: for each cap in caps[0..n_caps) it plans the
+ * teams of the chains (kg_batched_plan with keep_teams = 0, max_team = cap and
+ * the chains' m), copies the descriptors to chains_dev and times `reps`
+ * launches of grape_gradient_batched after one warm-up launch on `stream`
+ * (HIP events; ms_out[q] receives the mean time per launch of cap q,
+ * nullable).  It then plans the fastest cap into chains_host and chains_dev,
+ * writes it to *best_cap, and synchronises the stream before it returns (the
+ * one synchronous call of the batched form).  The buffers are those of
+ * grape_gradient_batched; ws must hold the plan of the largest cap.  The
+ * results in F_all, beta_all and grad_all are those of the last timed launch.
+ * Errors: KG_EINVAL, KG_EWORKSPACE, KG_EDEVICE. */
+kg_status kg_batched_autotune(kg_chain* chains_host, kg_chain* chains_dev, int32_t n_chains,
+                              int32_t n_blocks, const int32_t* caps, int32_t n_caps, int32_t reps,
+                              const double* u_all, int64_t u_len, const void* psi0_all,
+                              const void* target_all, int64_t vec_len, void* states_all,
+                              int64_t states_len, double* F_all, double* beta_all,
+                              double* grad_all, void* ws, size_t ws_bytes, int32_t* status_dev,
+                              float* ms_out, int32_t* best_cap, void* stream);
+
 /* F and dF/du for n_chains chains in one persistent launch.  chains_host holds
  * the descriptors for validation on the host; chains_dev is the same array in
  * device memory, read by the kernel (keep the two identical).  Array lengths:

@@ -52,6 +52,12 @@ class KgChain(ctypes.Structure):
                 ("off_ws", ctypes.c_int64)]
 
 
+class KgBatchPlan(ctypes.Structure):
+    _fields_ = [("u_len", ctypes.c_int64), ("vec_len", ctypes.c_int64),
+                ("states_len", ctypes.c_int64), ("ws_bytes", ctypes.c_uint64),
+                ("blocks_used", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
 class KgPe(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("K", ctypes.c_int32), ("dim", ctypes.c_int64),
                 ("tables", ctypes.c_void_p)]
@@ -96,6 +102,10 @@ SIGNATURES = {
     "kg_batched_chain_ws_bytes": (_SZ, [_I32, _I32, _I32]),
     "grape_gradient_batched": (_I32, [_P, _P, _I32, _I32, _P, ctypes.c_int64, _P, _P, ctypes.c_int64,
                                       _P, ctypes.c_int64, _P, _P, _P, _P, _SZ, _P, _P]),
+    "kg_batched_plan": (_I32, [_P, _I32, _P, _I32, _I32, _I32, _D, _I32, _I32, _P]),
+    "kg_batched_autotune": (_I32, [_P, _P, _I32, _I32, _P, _I32, _I32, _P, ctypes.c_int64, _P, _P,
+                                   ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, _P, _SZ, _P,
+                                   _P, _P, _P]),
     "kg_profile_end": (_I32, [_P, _P, _P]),
     "kg_columns_states_bytes": (_SZ, [_PX, _I32, _I32, _I32, _I32]),
     "grape_gradient_columns": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _I32, _P, _P, _P, _P, _P, _P,

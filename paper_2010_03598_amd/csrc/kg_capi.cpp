@@ -881,6 +881,206 @@ kg_status grape_gradient_batched(const kg_chain* chains_host, const kg_chain* ch
   return ok();
 }
 
+// ---------------------------------------------------------------------- batch planning
+
+namespace {
+
+constexpr int kBatchTile = 1024;   // amplitudes of a tile of the persistent kernel
+
+// Upper bound on the spectral radius of H0 + u Hc for |u| <= umax (Gershgorin on
+// the matrix elements of the open chain with S = sigma/2): each of the L-1 bonds
+// adds at most |J|/2 off the diagonal and |J Delta|/4 on it; S^x on one site adds
+// 1/2 off the diagonal, a sum of S^z over n sites at most n/2 on it.
+double gershgorin_norm(const kg_xxz& h, double umax) {
+  return (h.L - 1) * fabs(h.J) * (0.5 + fabs(h.Delta) / 4.0) +
+         fabs(umax) * 0.5 * (double)__builtin_popcountll(h.hc_sites);
+}
+
+// Hochbruck & Lubich (SIAM J. Numer. Anal. 34, 1997), Theorem 2: the error of the
+// m-dimensional Lanczos approximation of exp(A) v, A skew-Hermitian with its
+// spectrum on an imaginary segment of length 4 rho, is at most
+// 12 exp(-rho^2/m) (e rho/m)^m for m >= 2 rho.
+double hochbruck_lubich(double rho, int m) {
+  if (m < 2.0 * rho) return INFINITY;
+  return 12.0 * exp(-rho * rho / m) * pow(M_E * rho / m, (double)m);
+}
+
+// The smallest m in [m_min, m_max] whose bound for A = -i dt H meets tol / N.
+int krylov_dimension(const kg_xxz& h, double umax, double dt, int N, double tol, int m_min,
+                     int m_max) {
+  const double rho = 0.5 * fabs(dt) * gershgorin_norm(h, umax);
+  for (int m = m_min; m <= m_max; ++m)
+    if (hochbruck_lubich(rho, m) <= tol / N) return m;
+  return m_max;
+}
+
+// Vector traffic of one chain's gradient in amplitude passes: 2N Krylov calls of
+// about m^2 + 3m passes over 2^L amplitudes.
+double chain_work(const kg_chain& c) {
+  return 2.0 * c.N * ((double)c.m * c.m + 3.0 * c.m) * (double)((int64_t)1 << c.h.L);
+}
+
+}  // namespace
+
+kg_status kg_batched_plan(kg_chain* chains, int32_t n_chains, const double* umax, int32_t n_blocks,
+                          int32_t max_team, int32_t keep_teams, double tol, int32_t m_min,
+                          int32_t m_max, kg_batch_plan* plan) {
+  if (!chains || !plan) return fail(KG_EINVAL, "chains and plan are required");
+  if (n_chains < 1 || n_chains > 4096) return fail(KG_EINVAL, "n_chains=%d outside [1, 4096]", n_chains);
+  if (n_blocks < n_chains)
+    return fail(KG_EINVAL, "%d chains need at least %d workgroups, the grid has %d", n_chains,
+                n_chains, n_blocks);
+  if (max_team < 1 || max_team > 64) return fail(KG_EINVAL, "max_team=%d outside [1, 64]", max_team);
+  if (keep_teams != 0 && keep_teams != 1) return fail(KG_EINVAL, "keep_teams must be 0 or 1");
+  if (!(tol > 0.0) || !isfinite(tol)) return fail(KG_EINVAL, "tol must be finite and > 0");
+  if (m_min < 1 || m_max > KG_MAX_M || m_min > m_max)
+    return fail(KG_EINVAL, "Krylov range [%d, %d] outside [1, %d]", m_min, m_max, KG_MAX_M);
+  for (int i = 0; i < n_chains; ++i) {
+    kg_chain& c = chains[i];
+    KG_CHECK(check_xxz(&c.h));
+    if (c.h.L < 10 || c.h.L > 20) return fail(KG_EINVAL, "chain %d: L=%d outside [10, 20]", i, c.h.L);
+    if (c.N < 1) return fail(KG_EINVAL, "chain %d: N=%d", i, c.N);
+    if (!isfinite(c.dt)) return fail(KG_EINVAL, "chain %d: dt must be finite", i);
+    if (c.m == 0) {
+      if (!umax || !isfinite(umax[i]))
+        return fail(KG_EINVAL, "chain %d: m = 0 needs a finite umax", i);
+      c.m = krylov_dimension(c.h, umax[i], c.dt, c.N, tol, m_min, m_max);
+    } else if (c.m < 1 || c.m > KG_MAX_M) {
+      return fail(KG_EINVAL, "chain %d: m=%d", i, c.m);
+    }
+    if (keep_teams && (c.team_size < 1 || c.team_size > 64))
+      return fail(KG_EINVAL, "chain %d: team_size=%d outside [1, 64]", i, c.team_size);
+  }
+  if (!keep_teams) {
+    // greedy makespan balancing: one workgroup per chain, then double the team of
+    // the chain with the largest estimated time (work / team; the lowest index on
+    // ties) while its cap and the grid allow it
+    std::vector<int> cap(n_chains);
+    int used = n_chains;
+    for (int i = 0; i < n_chains; ++i) {
+      chains[i].team_size = 1;
+      const int tiles = (int)(((int64_t)1 << chains[i].h.L) / kBatchTile);
+      cap[i] = std::min(max_team, std::max(1, tiles));
+    }
+    for (;;) {
+      int best = 0;
+      for (int i = 1; i < n_chains; ++i)
+        if (chain_work(chains[i]) / chains[i].team_size >
+            chain_work(chains[best]) / chains[best].team_size)
+          best = i;
+      kg_chain& c = chains[best];
+      if (c.team_size * 2 > cap[best] || used + c.team_size > n_blocks) break;
+      used += c.team_size;
+      c.team_size *= 2;
+    }
+  }
+  int64_t off_u = 0, off_vec = 0, off_states = 0, off_ws = 0;
+  int first = 0;
+  for (int i = 0; i < n_chains; ++i) {
+    kg_chain& c = chains[i];
+    const int64_t D = (int64_t)1 << c.h.L;
+    c.team_first = first;
+    c.off_u = off_u;
+    c.off_vec = off_vec;
+    c.off_states = off_states;
+    c.off_ws = off_ws;
+    first += c.team_size;
+    off_u += c.N;
+    off_vec += D;
+    off_states += (int64_t)c.N * D;
+    off_ws += (int64_t)align_up(batched_chain_ws_bytes(c.h.L, c.m, c.team_size), 256);
+  }
+  if (first > n_blocks)
+    return fail(KG_EINVAL, "the teams need %d workgroups, the grid has %d", first, n_blocks);
+  plan->u_len = off_u;
+  plan->vec_len = off_vec;
+  plan->states_len = off_states;
+  plan->ws_bytes = (uint64_t)off_ws;
+  plan->blocks_used = first;
+  plan->pad_ = 0;
+  return ok();
+}
+
+kg_status kg_batched_autotune(kg_chain* chains_host, kg_chain* chains_dev, int32_t n_chains,
+                              int32_t n_blocks, const int32_t* caps, int32_t n_caps, int32_t reps,
+                              const double* u_all, int64_t u_len, const void* psi0_all,
+                              const void* target_all, int64_t vec_len, void* states_all,
+                              int64_t states_len, double* F_all, double* beta_all,
+                              double* grad_all, void* ws, size_t ws_bytes, int32_t* status_dev,
+                              float* ms_out, int32_t* best_cap, void* stream) {
+  if (!chains_host || !chains_dev || !caps || !best_cap)
+    return fail(KG_EINVAL, "chains, caps and best_cap are required");
+  if (n_chains < 1 || n_chains > 4096) return fail(KG_EINVAL, "n_chains=%d outside [1, 4096]", n_chains);
+  if (n_caps < 1 || n_caps > 16) return fail(KG_EINVAL, "n_caps=%d outside [1, 16]", n_caps);
+  if (reps < 1 || reps > 100) return fail(KG_EINVAL, "reps=%d outside [1, 100]", reps);
+  const hipStream_t s = (hipStream_t)stream;
+  std::vector<kg_chain> trial(chains_host, chains_host + n_chains);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  KG_HIP(hipEventCreate(&e0), "kg_batched_autotune");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(KG_EDEVICE, "kg_batched_autotune: event creation failed");
+  }
+  kg_status st = KG_OK;
+  float best_ms = INFINITY;
+  int best = -1;
+  const size_t desc_bytes = sizeof(kg_chain) * (size_t)n_chains;
+  for (int q = 0; q < n_caps && st == KG_OK; ++q) {
+    kg_batch_plan plan;
+    st = kg_batched_plan(trial.data(), n_chains, nullptr, n_blocks, caps[q], 0, 1.0, 1, KG_MAX_M,
+                         &plan);
+    if (st != KG_OK) break;
+    if (plan.ws_bytes > ws_bytes) {
+      st = fail(KG_EWORKSPACE, "cap %d needs %llu workspace bytes, %zu given", caps[q],
+                (unsigned long long)plan.ws_bytes, ws_bytes);
+      break;
+    }
+    hipError_t e = hipMemcpyAsync(chains_dev, trial.data(), desc_bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "kg_batched_autotune");
+      break;
+    }
+    // one launch to warm up, then `reps` timed
+    for (int r = 0; r <= reps && st == KG_OK; ++r) {
+      if (r == 1 && (e = hipEventRecord(e0, s)) != hipSuccess) st = hip_fail(e, "kg_batched_autotune");
+      if (st == KG_OK)
+        st = grape_gradient_batched(trial.data(), chains_dev, n_chains, n_blocks, u_all, u_len,
+                                    psi0_all, target_all, vec_len, states_all, states_len, F_all,
+                                    beta_all, grad_all, ws, ws_bytes, status_dev, stream);
+    }
+    if (st != KG_OK) break;
+    if ((e = hipEventRecord(e1, s)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+      st = hip_fail(e, "kg_batched_autotune");
+      break;
+    }
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+      st = hip_fail(e, "kg_batched_autotune");
+      break;
+    }
+    ms /= (float)reps;
+    if (ms_out) ms_out[q] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = q;
+    }
+  }
+  if (st == KG_OK) {
+    kg_batch_plan plan;
+    st = kg_batched_plan(chains_host, n_chains, nullptr, n_blocks, caps[best], 0, 1.0, 1, KG_MAX_M,
+                         &plan);
+    if (st == KG_OK) {
+      hipError_t e = hipMemcpyAsync(chains_dev, chains_host, desc_bytes, hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) st = hip_fail(e, "kg_batched_autotune");
+    }
+    if (st == KG_OK) *best_cap = caps[best];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st == KG_OK ? ok() : st;
+}
+
 kg_status kg_profile_begin(int32_t sample_every, int32_t max_launches) {
   if (g_prof) return fail(KG_EINVAL, "profiling is already active");
   if (sample_every < 1 || max_launches < 1 || max_launches > (1 << 22))

@@ -3,7 +3,8 @@ large to run the oracle inside a test (L=16 ascent, L=20 and L=24 chains).
 
 Calls only the oracle and the seeded input generators:
 
-    python tests/golden/make_golden.py [adjoint_short adjoint_full large_short large_ckpt
+    python tests/golden/make_golden.py [adjoint_short adjoint_short_plain adjoint_full
+                                        large_short large_ckpt
                                         ascent batched batched_planned]
 
 Each JSON file records the workload, the oracle settings and the values.
@@ -41,13 +42,15 @@ def chain_record(c):
             "N": c.N, "dt": c.dt, "m": c.m}
 
 
-def gradient_case(name, c, exact_slices=()):
+def gradient_case(name, c, exact_slices=(), reorth=True):
     t0 = time.time()
     ch = model.Chain(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
-    r = grape.gradient(ch, c.u, c.psi0, c.target, c.dt, c.m, True, krylov.default_tol())
+    r = grape.gradient(ch, c.u, c.psi0, c.target, c.dt, c.m, reorth, krylov.default_tol())
     rows = sample_rows(1 << c.L)
-    out = {"workload": name, "chain": chain_record(c), "reorth": True,
-           "oracle": "grape.gradient (Lanczos, full re-orthonormalisation, FP64)",
+    out = {"workload": name, "chain": chain_record(c), "reorth": reorth,
+           "oracle": "grape.gradient (Lanczos, " +
+                     ("full re-orthonormalisation" if reorth else "plain three-term window") +
+                     ", FP64)",
            "F": r.F, "beta": cplx(r.beta), "grad": r.grad.tolist(),
            "m_eff_fwd": r.m_eff_fwd.tolist(), "psi_N_rows": rows.tolist(),
            "psi_N_re": np.real(r.psi_N[rows]).tolist(), "psi_N_im": np.imag(r.psi_N[rows]).tolist()}
@@ -64,6 +67,11 @@ def gradient_case(name, c, exact_slices=()):
 def adjoint_short():
     c = workloads.adjoint(N=8)
     return gradient_case("adjoint L=20 with N=8 (seed 2)", c, exact_slices=range(8))
+
+
+def adjoint_short_plain():
+    c = workloads.adjoint(N=8)
+    return gradient_case("adjoint L=20 with N=8 (seed 2), plain Lanczos", c, reorth=False)
 
 
 def adjoint_full():
@@ -147,7 +155,8 @@ def batched_planned():
             "chains": recs, "oracle_seconds": time.time() - t0}
 
 
-CASES = {"adjoint_short": adjoint_short, "adjoint_full": adjoint_full,
+CASES = {"adjoint_short": adjoint_short, "adjoint_short_plain": adjoint_short_plain,
+         "adjoint_full": adjoint_full,
          "large_short": large_short, "large_ckpt": large_ckpt, "ascent": ascent,
          "batched": batched, "batched_planned": batched_planned}
 

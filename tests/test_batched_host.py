@@ -1,53 +1,124 @@
-"""Host logic of the batched form (no GPU): the Krylov-dimension choice meets its
-accuracy target on the oracle, and the team planner respects the grid."""
+"""Host logic of the batched form (no GPU): kg_batched_plan through the C ABI.
+Its Krylov dimensions equal the oracle's choice chain by chain (bit-exact
+integers), the stored batched golden was computed with those dimensions, and the
+team planner respects the grid, the caps and the packing."""
+
+import ctypes
+import json
+import os
 
 import numpy as np
 import pytest
-import scipy.linalg as sla
 
 import workloads
-from oracle import krylov, model
-from paper_2010_03598_amd import batched
+from oracle import dimension
+from paper_2010_03598_amd import _lib
+from paper_2010_03598_amd._lib import KgBatchPlan, KgChain, KgXxz
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TILE = 1024
 
 
-def test_error_bound_decreases_and_choice_meets_target_on_oracle():
-    L, J, Delta, dt, N = 10, 1.0, 1.5, 0.05, 300
-    m = batched.choose_m(L, J, Delta, 1, 1.0, dt, N)
-    assert 8 <= m <= 24
-    norm_h = (L - 1) * J * (0.5 + Delta / 4) + 0.5
-    b = [batched.lanczos_error_bound(0.5 * norm_h * dt, k) for k in range(6, 25)]
-    assert all(x >= y for x, y in zip(b, b[1:]))
-    assert batched.lanczos_error_bound(0.5 * norm_h * dt, m) <= 1e-8 / N
-    # the oracle's Krylov propagation at the chosen m reaches the target against expm
-    rng = np.random.default_rng(0)
-    psi = workloads.random_state(rng, 1 << L)
-    ch = model.Chain(L, J, Delta, 0, 1)
-    H = model.xxz_dense(L, J, Delta) + 1.0 * model.hc_dense(L, 0, 1)
-    out = krylov.expv(lambda v: ch.apply(1.0, v), psi, dt, m, True)
-    assert np.linalg.norm(out - sla.expm(-1j * dt * H) @ psi) <= 1e-8 / N
+def c_plan(chains, n_blocks, max_team=64, teams=None, tol=1e-8, m_min=8, m_max=24, ms=None):
+    n = len(chains)
+    descs = (KgChain * n)()
+    umax = (ctypes.c_double * n)()
+    for i, c in enumerate(chains):
+        d = descs[i]
+        d.h = KgXxz(c.L, c.hc_kind, c.J, c.Delta, c.hc_sites)
+        d.N, d.m, d.reorth, d.dt = c.N, 0 if ms is None else ms[i], 1, c.dt
+        d.team_size = 0 if teams is None else teams[i]
+        umax[i] = float(np.abs(c.u).max())
+    p = KgBatchPlan()
+    st = _lib.load().kg_batched_plan(ctypes.cast(descs, ctypes.c_void_p), n,
+                                     ctypes.cast(umax, ctypes.c_void_p), n_blocks, max_team,
+                                     0 if teams is None else 1, tol, m_min, m_max,
+                                     ctypes.byref(p))
+    return st, descs, p
 
 
-def test_choose_m_on_batched_workload():
-    ms = [batched.choose_m(c.L, c.J, c.Delta, 1, float(np.abs(c.u).max()), c.dt, c.N)
-          for c in workloads.batched()]
-    assert min(ms) >= 8 and max(ms) <= 24
+def oracle_m(c, tol=1e-8):
+    return dimension.krylov_dimension(c.L, c.J, c.Delta, bin(c.hc_sites).count("1"),
+                                      float(np.abs(c.u).max()), c.dt, c.N, tol)
 
 
-class FakeChain:
-    def __init__(self, L, N, m):
-        self.h = type("H", (), {"L": L})()
-        self.N, self.m = N, m
+def test_dimensions_equal_the_oracle_choice():
+    chains = workloads.batched()
+    st, descs, _ = c_plan(chains, 256)
+    assert st == _lib.KG_OK, _lib.last_error()
+    assert [d.m for d in descs] == [oracle_m(c) for c in chains]
+    # a tighter and a looser accuracy move the choice the same way on both sides
+    for tol in (1e-12, 1e-4):
+        st, descs, _ = c_plan(chains[:16], 256, tol=tol)
+        assert [d.m for d in descs] == [oracle_m(c, tol) for c in chains[:16]]
 
 
-def test_plan_teams_fits_grid_and_balances():
-    rng = np.random.default_rng(3)
-    chains = [FakeChain(int(rng.integers(10, 17)), int(rng.integers(50, 301)), 12) for _ in range(64)]
-    teams = batched.plan_teams(chains, 256)
-    assert len(teams) == 64 and sum(teams) <= 256 and min(teams) >= 1
+def test_golden_batch_was_computed_with_the_planned_dimensions():
+    with open(os.path.join(GOLDEN, "batched_planned.json")) as fh:
+        gold = json.load(fh)
+    _, descs, _ = c_plan(workloads.batched(), 256)
+    assert [d.m for d in descs] == [rec["chain"]["m"] for rec in gold["chains"]]
+
+
+def work(c, m):
+    return 2.0 * c.N * (m * m + 3 * m) * (1 << c.L)
+
+
+@pytest.mark.parametrize("n_blocks,max_team", [(256, 64), (128, 8), (64, 1), (300, 16)])
+def test_teams_fit_grid_caps_and_balance(n_blocks, max_team):
+    chains = workloads.batched()
+    st, descs, p = c_plan(chains, n_blocks, max_team)
+    assert st == _lib.KG_OK, _lib.last_error()
+    teams = [d.team_size for d in descs]
+    assert sum(teams) == p.blocks_used <= n_blocks and min(teams) >= 1
     for c, t in zip(chains, teams):
-        assert t <= max(1, (1 << c.h.L) // batched.TILE) and (t & (t - 1)) == 0
-    span = max(batched.work(c) / t for c, t in zip(chains, teams))
-    naive = max(batched.work(c) for c in chains)
-    assert span <= naive
-    with pytest.raises(ValueError):
-        batched.plan_teams(chains, 10)
+        assert t <= min(max_team, max(1, (1 << c.L) // TILE)) and (t & (t - 1)) == 0
+    # the greedy stops at the chain with the largest time per workgroup; growing
+    # its team further is blocked by its cap or by the grid
+    span = [work(c, d.m) / d.team_size for c, d in zip(chains, descs)]
+    i = int(np.argmax(span))
+    cap = min(max_team, max(1, (1 << chains[i].L) // TILE))
+    assert teams[i] * 2 > cap or p.blocks_used + teams[i] > n_blocks
+    assert max(span) <= max(work(c, d.m) for c, d in zip(chains, descs))
+
+
+def test_packing_is_contiguous():
+    chains = workloads.batched()[:9]
+    st, descs, p = c_plan(chains, 64)
+    assert st == _lib.KG_OK
+    off_u = off_vec = off_states = off_ws = first = 0
+    for c, d in zip(chains, descs):
+        assert (d.off_u, d.off_vec, d.off_states, d.off_ws, d.team_first) == \
+               (off_u, off_vec, off_states, off_ws, first)
+        assert d.off_ws % 256 == 0
+        wsb = _lib.load().kg_batched_chain_ws_bytes(c.L, d.m, d.team_size)
+        off_u += c.N
+        off_vec += 1 << c.L
+        off_states += c.N << c.L
+        off_ws += (wsb + 255) // 256 * 256
+        first += d.team_size
+    assert (p.u_len, p.vec_len, p.states_len, p.ws_bytes) == (off_u, off_vec, off_states, off_ws)
+
+
+def test_kept_teams_and_given_dimensions():
+    chains = workloads.batched()[:5]
+    st, descs, p = c_plan(chains, 32, teams=[1, 2, 4, 1, 2], ms=[9, 10, 11, 12, 13])
+    assert st == _lib.KG_OK
+    assert [d.team_size for d in descs] == [1, 2, 4, 1, 2]
+    assert [d.m for d in descs] == [9, 10, 11, 12, 13]
+    assert [d.team_first for d in descs] == [0, 1, 3, 7, 8]
+
+
+@pytest.mark.parametrize("kw", [dict(n_blocks=3), dict(n_blocks=64, max_team=0),
+                                dict(n_blocks=64, max_team=65), dict(n_blocks=64, tol=0.0),
+                                dict(n_blocks=64, m_min=10, m_max=9)])
+def test_invalid_arguments(kw):
+    chains = workloads.batched()[:5]
+    st, _, _ = c_plan(chains, **kw)
+    assert st == _lib.KG_EINVAL and _lib.last_error()
+
+
+def test_grid_too_small_for_kept_teams():
+    chains = workloads.batched()[:3]
+    st, _, _ = c_plan(chains, 4, teams=[2, 2, 2])
+    assert st == _lib.KG_EINVAL

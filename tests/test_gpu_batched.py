@@ -111,6 +111,25 @@ def test_full_batched_workload_vs_oracle():
         assert rel_err(host(b.grad_of(i)), np.array(rec["grad"])) <= 1e-4, i
 
 
+def test_autotuned_planned_workload_vs_oracle():
+    """The 64-chain workload as the bench times it: Krylov dimensions chosen by the
+    C planner, team shapes by the C autotuner; against the oracle run with the
+    same dimensions (tests/golden/batched_planned.json)."""
+    with open(os.path.join(GOLDEN, "batched_planned.json")) as fh:
+        gold = json.load(fh)
+    ws = workloads.batched()
+    b, info = batched.autotune(batched.from_workload(ws), caps=(2, 8, 32))
+    assert b.m == [rec["chain"]["m"] for rec in gold["chains"]]
+    assert info["best_cap"] in (2, 8, 32) and sum(b.teams) <= b.n_blocks
+    b.gradient()
+    torch.cuda.synchronize()
+    b.check_status()
+    F = host(b.F)
+    for i, rec in enumerate(gold["chains"]):
+        assert abs(F[i] - rec["F"]) / rec["F"] <= 1e-4, i
+        assert rel_err(host(b.grad_of(i)), np.array(rec["grad"])) <= 1e-4, i
+
+
 def test_autotuned_batch_runs():
     ws = workloads.batched()[:16]
     chains = batched.from_workload(ws)

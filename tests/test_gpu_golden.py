@@ -72,3 +72,26 @@ def test_ascent_run_every_iteration():
         kg.grape_ascent_update(u, r.grad, gold["eta"])
     assert np.abs(host(u) - np.array(gold["u_final"])).max() <= 1e-10
     assert Fs[-1] > Fs[0]
+
+
+def gradient_vs_golden(name, c, dtype, tol, ckpt_every, reorth=True):
+    gold = load_golden(name)
+    assert gold["reorth"] == reorth and gold["chain"]["N"] == c.N
+    h = xxz_of(c)
+    u = torch.tensor(c.u, dtype=torch.float64, device="cuda")
+    r = kg.grape_gradient(h, u, c.dt, kg.Krylov(c.m, reorth), dev_vec(c.psi0, dtype),
+                          dev_vec(c.target, dtype), ckpt_every=ckpt_every)
+    F = float(host(r.F))
+    assert abs(F - gold["F"]) / gold["F"] <= tol
+    g = host(r.grad)
+    gref = np.array(gold["grad"])
+    assert rel_err(g, gref) <= tol
+    assert np.abs(g - gref).max() / np.abs(gref).max() <= tol
+    b = host(r.beta)
+    assert abs(complex(b[0], b[1]) - complex(*gold["beta"])) / abs(complex(*gold["beta"])) <= tol
+
+
+@pytest.mark.parametrize("dtype,tol", [(C128, 1e-10), (C64, 1e-4)])
+def test_adjoint_plain_lanczos(dtype, tol):
+    """Plain Lanczos (three-term window) policy to policy: L=20, N=8, m=20."""
+    gradient_vs_golden("adjoint_short_plain", workloads.adjoint(N=8), dtype, tol, 4, reorth=False)
