@@ -155,6 +155,23 @@ kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, i
                       const void* v_in, void* v_out, void* ws, size_t ws_bytes,
                       int32_t* m_eff_dev, void* stream);
 
+/* krylov_expv for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation, kernels and results, with the scratch in a static device
+ * array of kg_static_scratch_bytes() (64 MiB) that each GPU the library runs on
+ * holds until the process ends, instead of a caller's workspace.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine); the
+ * caller still passes the vectors.  It needs one Krylov slot, 4.4 MB of
+ * scalars and partials plus m vectors of 2^L amplitudes (for example L <= 18
+ * with m <= 25 in complex64, L <= 17 with m <= 25 in complex128); larger
+ * problems fail with KG_EWORKSPACE and a message.  Every call on a GPU shares
+ * that GPU's array and leaves its contents there: calls that overlap on one
+ * GPU (other streams, other host threads) race and must be serialised by the
+ * caller.  Errors: KG_EINVAL, KG_EWORKSPACE, KG_EDEVICE. */
+size_t kg_static_scratch_bytes(void);
+kg_status krylov_expv_static(const kg_xxz* h, double u, double t, const kg_krylov* k, int32_t prec,
+                             const void* v_in, void* v_out, int32_t* m_eff_dev, void* stream);
+
 /* Forward sweep of Algorithm 1 (Eqs. 2, 4, B1, B2): psi_j = exp(-i dt H_j)
  * psi_{j-1}, H_j = H0 + u_j Hc, j = 1..N, with u_dev[j-1] = u_j.  Writes
  * beta = <target|psi_N> to beta_dev[0..1] (re, im) and F = |beta|^2 to

@@ -107,6 +107,8 @@ SIGNATURES = {
                                    ctypes.c_int64, _P, ctypes.c_int64, _P, _P, _P, _P, _SZ, _P,
                                    _P, _P, _P]),
     "kg_profile_end": (_I32, [_P, _P, _P]),
+    "kg_static_scratch_bytes": (_SZ, []),
+    "krylov_expv_static": (_I32, [_PX, _D, _D, _PK, _I32, _P, _P, _P, _P]),
     "kg_columns_states_bytes": (_SZ, [_PX, _I32, _I32, _I32, _I32]),
     "grape_gradient_columns": (_I32, [_PX, _P, _I32, _D, _PK, _I32, _I32, _P, _P, _P, _P, _P, _P,
                                       _P, _I32, _I32, _P, _SZ, _P]),

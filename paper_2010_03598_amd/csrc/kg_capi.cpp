@@ -750,6 +750,57 @@ kg_status krylov_expv(const kg_xxz* h, double u, double t, const kg_krylov* k, i
   return expv_impl(h, sp, u, t, k, prec, v_in, v_out, ws, ws_bytes, m_eff_dev, stream);
 }
 
+size_t kg_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+kg_status krylov_expv_static(const kg_xxz* h, double u, double t, const kg_krylov* k, int32_t prec,
+                             const void* v_in, void* v_out, int32_t* m_eff_dev, void* stream) {
+  KG_CHECK(check_xxz(h));
+  KG_CHECK(check_krylov(k));
+  KG_CHECK(check_prec(prec));
+  if (!isfinite(u) || !isfinite(t)) return fail(KG_EINVAL, "u and t must be finite");
+  KG_CHECK(check_vec(v_in, prec, "v_in"));
+  KG_CHECK(check_vec(v_out, prec, "v_out"));
+  const Geo geo = make_geo(h->L, prec, tile_override_from_env());
+  if (v_in != v_out && overlap(v_in, v_out, vbytes(geo.D, prec)))
+    return fail(KG_EINVAL, "v_in and v_out overlap without being equal");
+  if (m_eff_dev && (uintptr_t)m_eff_dev % 4) return fail(KG_EINVAL, "m_eff_dev misaligned");
+  // one Krylov slot (scalars, partials, m-1 basis vectors and H v_k)
+  const size_t need = slot_bytes_d(geo.D, k, prec);
+  if (need > kStaticScratchBytes)
+    return fail(KG_EWORKSPACE,
+                "krylov_expv_static: L=%d, m=%d needs %zu bytes of scratch, the static "
+                "scratch holds %zu (use krylov_expv with a workspace)",
+                h->L, k->m, need, kStaticScratchBytes);
+  void* base = nullptr;
+  KG_HIP(static_scratch(&base), "krylov_expv_static scratch address");
+  char* q = static_cast<char*>(base);
+  Workspace W;
+  memset(&W, 0, sizeof(W));
+  W.st = reinterpret_cast<KState*>(q);
+  q += align_up(sizeof(KState), 256);
+  W.partials = reinterpret_cast<cplx_d*>(q);
+  q += align_up(sizeof(cplx_d) * kPartialRows * kMaxScal, 256);
+  W.basis = q;
+  q += align_up(vbytes(geo.D, prec) * (size_t)(k->m - 1), 256);
+  W.yk = q;
+  const hipStream_t s = (hipStream_t)stream;
+  KrylovCall c;
+  c.hv = make_hv(h, nullptr, u);
+  c.geo = geo;
+  c.pe = nullptr;
+  c.prec = prec;
+  c.m = k->m;
+  c.reorth = k->reorth;
+  c.t = t;
+  c.tol = k->breakdown_tol > 0.0 ? k->breakdown_tol : default_tol(prec);
+  c.v_in = v_in;
+  c.v_out = v_out;
+  c.m_eff_out = m_eff_dev;
+  KG_HIP(launch_init(W.st, s), "krylov_expv_static init");
+  KG_HIP(launch_krylov(c, W, s), "krylov_expv_static");
+  return ok();
+}
+
 kg_status grape_forward(const kg_xxz* h, const double* u_dev, int32_t N, double dt,
                         const kg_krylov* k, int32_t prec, const void* psi0, const void* target,
                         double* F_dev, double* beta_dev, void* states, int32_t ckpt_every, void* ws,

@@ -145,6 +145,11 @@ hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam
 hipError_t launch_hv_pe(int prec, const HvArgs& a, const PeArgs& p, const void* v, void* w,
                         hipStream_t s);
 hipError_t launch_init(KState* st, hipStream_t s);
+
+// Scratch of krylov_expv_static (kg_static.hip): a device array of this many
+// bytes per GPU; *ptr receives its device address on the current device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+hipError_t static_scratch(void** ptr);
 hipError_t launch_ascent(double* u, const double* g, int N, double eta, hipStream_t s);
 hipError_t launch_centre(double* g, int N, const double* g0, hipStream_t s);
 hipError_t launch_mean_overlap(const double* beta_cols, int n, double* beta, double* F,
