@@ -9,7 +9,9 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libkgrape.so")
+# the in-tree build; KG_LIBRARY names another build of the same sources (the
+# host-sanitizer build that the CPU tests load in a child process)
+LIB_PATH = os.environ.get("KG_LIBRARY") or os.path.join(_PKG, "libkgrape.so")
 
 KG_OK = 0
 KG_EINVAL = -1
