@@ -434,9 +434,9 @@ def fig2b(kg, torch, workloads, sizes, max_iter=300):
 def batched_algorithmic_bytes(chains, ms):
     """Bytes the batched launch must move (complex64 vectors, 8 B per amplitude):
     per chain, 2N-1 Krylov calls (store-all: no recomputation), each with pass A
-    reading its window and writing y (no y in the last step), pass B reading y
-    and the window and writing the next vector, and the combination reading
-    m vectors and writing one; N brackets and the overlap read two vectors."""
+    reading v_k and writing y (no y in the last step), pass B reading y and the
+    window and writing the next vector, and the combination reading m vectors
+    and writing one; N brackets and the overlap read two vectors."""
     total = 0
     for c, m in zip(chains, ms):
         V = 8 << c.h.L
@@ -444,7 +444,7 @@ def batched_algorithmic_bytes(chains, ms):
         for k in range(m):
             last = k == m - 1
             nw = 1 if last else (k + 1 if c.reorth else min(k + 1, 2))
-            per_call += (nw + (0 if last else 1)) + (0 if last else nw + 2)
+            per_call += (1 + (0 if last else 1)) + (0 if last else nw + 2)
         per_call += m + 1
         total += V * ((2 * c.N - 1) * per_call + 2 * c.N + 2)
     return total

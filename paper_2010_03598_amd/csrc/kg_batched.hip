@@ -138,13 +138,21 @@ __device__ bool team_reduce(BCtx& c, cplx_d* tot, int ns) {
   return true;
 }
 
-// Scalars of the running Krylov call, held in LDS by every member.
+// Scalars of the running Krylov call, held in LDS by every member (every member
+// computes them from the same team sums, so all hold the same values).  The
+// projection coefficients and the measured Gram columns are kept for two
+// steps, by the parity of the step; cdiag/csub are step i's coefficients on
+// the stored vector i itself and on vector i-1.
 struct KScal {
   double alpha[kMaxM];
   double offd[kMaxM + 1];
   double scale[kMaxM + 1];
-  cplx_d coef[kMaxM];
+  cplx_d coef[2][kMaxM];
   cplx_d dcomb[kMaxM];
+  cplx_d cdiag[kMaxM];
+  cplx_d csub[kMaxM];
+  cplx_d gcol[2][kMaxM];
+  cplx_d bmeas[kMaxScal];   // this member's pass B measurements, for the next step's sums
   double beta0;
   double normT;
   int m_eff;
@@ -156,8 +164,17 @@ __device__ __forceinline__ const float2* bslot(const BCtx& c, const float2* in, 
 }
 
 // One Krylov call exp(-i t H) in -> out for the team (out may equal in).
+// Each step k is two passes over the member's tiles, as in the single-chain
+// kernels: pass A forms y = H v_k and only <v_k|y>, ||v_k||^2; the team sums
+// them together with pass B(k-1)'s measurements, and every member runs the
+// scalar update (breakdown test, window dots derived from the measurements,
+// projection coefficients); pass B then reads the window once to form
+// w = s_k y - sum_i c_i v_i and measures <v_j|y> and <v_j|v_k> for the next
+// step's window dots.  A team barrier after pass B makes v_{k+1} visible to
+// the members that read its tiles as H v partners.
 __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, const float2* in,
-                            float2* out, KScal& K, float2* lds, cplx_d* wacc, cplx_d* tot) {
+                            float2* out, KScal& K, float2* lds, cplx_d* wacc, cplx_d* tot,
+                            FinScalars& fs) {
   using V = float2;
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
@@ -170,114 +187,149 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
     K.m_eff = m;
   }
   __syncthreads();
+  int i0p = 0;
   for (int k = 0; k < m; ++k) {
     const bool last = (k == m - 1);
     const int i0 = last ? k : (ch.reorth ? 0 : (k > 0 ? k - 1 : 0));
+    const int i0n = (k + 1 == m - 1) ? k + 1 : (ch.reorth ? 0 : k);
     const int nwin = k - i0 + 1;
+    // window dots of step k come from pass B(k-1)'s measurements of nb vectors
+    const int nb = (k > 0 && i0 < k) ? k - i0p : 0;
+    const int ca = 2 * nb, ns = ca + 2;
     const float2* x = bslot(c, in, k);
-    // ---- pass A(k): y = H x, <v_i|y> over the window, <x|x>
-    double acc_re = 0.0, acc_im = 0.0, acc_nn = 0.0;
+    // ---- pass A(k): y = H x, <x|y> and <x|x>
+    double acc = 0.0;
     for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
       __syncthreads();
       hv_tile<float, kBRB, true>(T, c.hv, c.geo, tile, x, lds, u);
       const uint32_t s = (tile << kBTB) | lane | (wv << 6);
-      const double yr = T.yr[0], yi = T.yi[0];
       if (!last) c.ybuf[s] = V{T.yr[0], T.yi[0]};   // for pass B of this member
-      for (int i = i0; i < k; i += 8) {
-        V q[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j)
-          if (i + j < k) q[j] = bslot(c, in, i + j)[s];
-        // two window vectors' dots per wavefront sum: quad_sums leaves value v
-        // of {Re, Im of vector j, Re, Im of vector j+1} in lane v
-#pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-          if (i + j < k) {
-            const bool two = i + j + 1 < k;
-            const double s0 = (double)q[j].x * yr + (double)q[j].y * yi;
-            const double s1 = (double)q[j].x * yi - (double)q[j].y * yr;
-            const double s2 = two ? (double)q[j + 1].x * yr + (double)q[j + 1].y * yi : 0.0;
-            const double s3 = two ? (double)q[j + 1].x * yi - (double)q[j + 1].y * yr : 0.0;
-            const double t = quad_sums(s0, s1, s2, s3);
-            if ((int)lane == i + j - i0) {
-              acc_re += lane_value(t, 0);
-              acc_im += lane_value(t, 1);
-            }
-            if (two && (int)lane == i + j + 1 - i0) {
-              acc_re += lane_value(t, 2);
-              acc_im += lane_value(t, 3);
-            }
+      const double xr = T.xr[0], xi = T.xi[0], yr = T.yr[0], yi = T.yi[0];
+      acc += quad_sums(xr * yr + xi * yi, xr * yi - xi * yr, xr * xr + xi * xi, 0.0);
+    }
+    __syncthreads();
+    if (lane < 4u) reinterpret_cast<double*>(&wacc[wv * kMaxScal + ca])[lane] = (lane < 3u) ? acc : 0.0;
+    // pass B(k-1)'s block totals join the sums of this step
+    for (int j = threadIdx.x; j < ca; j += blockDim.x) tot[j] = K.bmeas[j];
+    if (k > 0 && threadIdx.x == 0) tot[ns] = K.bmeas[ca];
+    __syncthreads();
+    block_totals(wacc, ns, tot, ca);
+    if (!team_reduce(c, tot, k > 0 ? ns + 1 : ns)) return false;
+    // ---- scalar update of step k on wavefront 0 of every member
+    if (threadIdx.x < 64) {
+      const int l = threadIdx.x;
+      if (k > 0) {
+        // the earlier steps' scalars for the window dots, staged from K
+        fs.alpha[l] = K.alpha[l];
+        fs.offd[l] = K.offd[l];
+        fs.scale[l] = K.scale[l];
+        fs.coef[l] = K.coef[(k - 1) & 1][l];
+        fs.gprev[l] = K.gcol[k & 1][l];
+        fs.cdiag[l] = K.cdiag[l];
+        fs.csub[l] = K.csub[l];
+        if (l == 0) {
+          fs.normT = K.normT;
+          fs.beta0 = K.beta0;
+        }
+      }
+      bool go = true;
+      double sk = 0.0, bk = 0.0;
+      if (k == 0) {
+        const double nn = tot[ca + 1].re;
+        if (!(nn > 0.0)) {
+          // a zero input gives a zero output; a non-finite one a NaN output
+          go = false;
+          if (l == 0) {
+            K.beta0 = (nn == 0.0) ? 0.0 : NAN;
+            K.m_eff = (nn == 0.0) ? 0 : 1;
+            K.alpha[0] = 0.0;
+            K.scale[0] = 1.0;
+            K.done = 1;
+          }
+        } else {
+          sk = 1.0 / sqrt(nn);
+          if (l == 0) {
+            K.beta0 = sqrt(nn);
+            K.scale[0] = sk;
+            K.offd[0] = 0.0;
+          }
+        }
+      } else {
+        // ||w|| of pass B(k-1): the off-diagonal entry of step k, or a breakdown
+        bk = sqrt(tot[ns].re);
+        if (bk <= tol * fmax(1.0, fs.normT)) {
+          go = false;
+          if (l == 0) {
+            K.m_eff = k;
+            K.done = 1;
+          }
+        } else {
+          sk = 1.0 / bk;
+          if (l == 0) {
+            K.offd[k] = bk;
+            K.scale[k] = sk;
           }
         }
       }
-      {
-        const double xr = T.xr[0], xi = T.xi[0];
-        const double t = quad_sums(xr * yr + xi * yi, xr * yi - xi * yr, xr * xr + xi * xi, 0.0);
-        if ((int)lane == k - i0) {
-          acc_re += lane_value(t, 0);
-          acc_im += lane_value(t, 1);
-        }
-        acc_nn += lane_value(t, 2);
-      }
-    }
-    __syncthreads();
-    if ((int)lane < nwin) wacc[wv * kMaxScal + lane] = cplx_d{acc_re, acc_im};
-    if (lane == 0) wacc[wv * kMaxScal + nwin] = cplx_d{acc_nn, 0.0};
-    __syncthreads();
-    block_totals(wacc, nwin + 1, tot);
-    if (!team_reduce(c, tot, nwin + 1)) return false;
-    if (threadIdx.x == 0) {
-      double sk;
-      bool zero = false;
-      if (k == 0) {
-        const double nn = tot[nwin].re;
-        if (nn == 0.0) {
-          zero = true;
-          K.beta0 = 0.0;
-          K.m_eff = 0;
-          K.done = 1;
-        } else if (!(nn > 0.0)) {
-          // a non-finite input: exp(0) times NaN, so the output is NaN
-          zero = true;
-          K.beta0 = NAN;
-          K.m_eff = 1;
-          K.alpha[0] = 0.0;
-          K.scale[0] = 1.0;
-          K.done = 1;
-        } else {
-          K.beta0 = sqrt(nn);
-          K.scale[0] = 1.0 / K.beta0;
-          K.offd[0] = 0.0;
-        }
-      }
-      if (!zero) {
-        sk = K.scale[k];
-        for (int l = 0; l < nwin; ++l) {
+      if (go) {
+        const cplx_d d = (nb > 0) ? window_dots(k, i0, i0p, fs, tot, nb, tot[ns].re, K.gcol[(k - 1) & 1])
+                                  : cplx_d{0.0, 0.0};
+        if (l < nwin) {
           const int i = i0 + l;
-          const double si = K.scale[i];
+          const double si = (i == k) ? sk : K.scale[i];
           const double f = si * sk;
-          K.coef[l] = cplx_d{tot[l].re * f * si, tot[l].im * f * si};
+          const cplx_d tt = (i == k) ? tot[ca] : d;
+          const cplx_d cc{tt.re * f * si, tt.im * f * si};
+          K.coef[k & 1][l] = cc;
+          if (i == k) K.cdiag[k] = cc;
+          if (i == k - 1) K.csub[k] = cc;
         }
-        const double alpha = tot[nwin - 1].re * sk * sk;
-        K.alpha[k] = alpha;
-        K.normT = fmax(k == 0 ? 0.0 : K.normT, fabs(alpha) + (k == 0 ? 0.0 : K.offd[k]));
-        if (last) {
-          K.m_eff = m;
-          K.done = 1;
+        const double alpha = tot[ca].re * sk * sk;
+        if (l == 0) {
+          K.alpha[k] = alpha;
+          K.normT = fmax(k == 0 ? 0.0 : fs.normT, fabs(alpha) + (k == 0 ? 0.0 : bk));
+          if (last) {
+            K.m_eff = m;
+            K.done = 1;
+          }
         }
       }
     }
     __syncthreads();
+    i0p = i0;
     if (K.done) break;
-    // ---- pass B(k): w = s_k y - sum_i coef_i v_i -> stored v_{k+1}, ||w||^2
+    // ---- pass B(k): w = s_k y - sum_i c_i v_i -> stored v_{k+1}; ||w||^2 and,
+    // when step k+1 has window dots, <v_j|y> (columns [0, nbo)) and <v_j|v_k>
+    // (columns [nbo, 2nbo)) for the window vectors j
+    const int nbo = (i0n <= k) ? nwin : 0;
     const double sk = K.scale[k];
+    const cplx_d* cf = K.coef[k & 1];
     float2* vout = c.basis + (size_t)k * c.geo.D;
+    cplx_d* wrow = wacc + wv * kMaxScal;
+    for (int j = (int)lane; j < 2 * nbo; j += 64) wrow[j] = cplx_d{0.0, 0.0};
     double bnn = 0.0;
+    const auto add_quad = [&](int w, double tq) {
+      if (lane < 4u) {
+        cplx_d& d = wrow[(lane < 2u ? 0 : nbo) + w];
+        if (lane & 1u) {
+          d.im += tq;
+        } else {
+          d.re += tq;
+        }
+      }
+    };
     for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
       const uint32_t s = (tile << kBTB) | lane | (wv << 6);
       const V yv = c.ybuf[s];
       const V xv = x[s];
-      double zr = sk * (double)yv.x, zi = sk * (double)yv.y;
+      const double yr = yv.x, yi = yv.y, xr = xv.x, xi = xv.y;
+      double zr, zi;
+      {
+        const cplx_d cc = cf[k - i0];
+        zr = sk * yr - (cc.re * xr - cc.im * xi);
+        zi = sk * yi - (cc.re * xi + cc.im * xr);
+      }
+      if (nbo) add_quad(k - i0, quad_sums(xr * yr + xi * yi, xr * yi - xi * yr, xr * xr + xi * xi, 0.0));
       for (int i = i0; i < k; i += 8) {
         V q[8];
 #pragma unroll
@@ -286,16 +338,15 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           if (i + j < k) {
-            const cplx_d cc = K.coef[i + j - i0];
-            zr -= cc.re * (double)q[j].x - cc.im * (double)q[j].y;
-            zi -= cc.re * (double)q[j].y + cc.im * (double)q[j].x;
+            const cplx_d cc = cf[i + j - i0];
+            const double vr = q[j].x, vi = q[j].y;
+            zr -= cc.re * vr - cc.im * vi;
+            zi -= cc.re * vi + cc.im * vr;
+            if (nbo)
+              add_quad(i + j - i0, quad_sums(vr * yr + vi * yi, vr * yi - vi * yr,
+                                             vr * xr + vi * xi, vr * xi - vi * xr));
           }
         }
-      }
-      {
-        const cplx_d cc = K.coef[k - i0];
-        zr -= cc.re * (double)xv.x - cc.im * (double)xv.y;
-        zi -= cc.re * (double)xv.y + cc.im * (double)xv.x;
       }
       V o;
       o.x = (float)zr;
@@ -303,23 +354,11 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
       st_coh(&vout[s], o);      // read by other members as H v partners
       bnn += wave_sum((double)o.x * (double)o.x + (double)o.y * (double)o.y);
     }
+    if (lane == 0) wrow[2 * nbo] = cplx_d{bnn, 0.0};
     __syncthreads();
-    if (lane == 0) wacc[wv * kMaxScal] = cplx_d{bnn, 0.0};
-    __syncthreads();
-    block_totals(wacc, 1, tot);
-    if (!team_reduce(c, tot, 1)) return false;
-    if (threadIdx.x == 0) {
-      const double b = sqrt(tot[0].re);
-      if (b <= tol * fmax(1.0, K.normT)) {
-        K.m_eff = k + 1;
-        K.done = 1;
-      } else {
-        K.offd[k + 1] = b;
-        K.scale[k + 1] = 1.0 / b;
-      }
-    }
-    __syncthreads();
-    if (K.done) break;
+    block_totals(wacc, 2 * nbo + 1, K.bmeas);
+    // v_{k+1} complete in every member before any member reads its partners
+    if (!team_barrier(c)) return false;
   }
   // ---- exp(-itT) e_1 on wavefront 0 and the combination coefficients
   const int me = K.m_eff;
@@ -401,6 +440,7 @@ __global__ void __launch_bounds__(kBThreads)
   cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
   __shared__ cplx_d tot[kMaxScal];
   __shared__ KScal K;
+  __shared__ FinScalars fs;
 
   // the chain of this workgroup
   int cid = -1;
@@ -464,7 +504,7 @@ __global__ void __launch_bounds__(kBThreads)
   for (int j = 1; j <= ch.N; ++j) {
     c.hv.u_ptr = u + (j - 1);
     float2* out = states + (size_t)(j - 1) * D;
-    if (!team_krylov(c, ch, ch.dt, tol, prev, out, K, lds, wacc, tot)) return;
+    if (!team_krylov(c, ch, ch.dt, tol, prev, out, K, lds, wacc, tot, fs)) return;
     prev = out;
   }
   cplx_d beta;
@@ -482,7 +522,7 @@ __global__ void __launch_bounds__(kBThreads)
     if (c.member == 0 && threadIdx.x == 0) grad[j - 1] = 2.0 * ch.dt * (beta.re * B.im - beta.im * B.re);
     if (j > 1) {
       c.hv.u_ptr = u + (j - 1);
-      if (!team_krylov(c, ch, -ch.dt, tol, lam, c.lam, K, lds, wacc, tot)) return;
+      if (!team_krylov(c, ch, -ch.dt, tol, lam, c.lam, K, lds, wacc, tot, fs)) return;
       lam = c.lam;
     }
   }

@@ -223,19 +223,6 @@ __device__ __forceinline__ const V* slot_ptr(const LzArgs& a, int i) {
                 : reinterpret_cast<const V*>(a.basis) + (size_t)(i - 1) * a.geo.D;
 }
 
-// KState values of the earlier steps that the scalar update of step k reads,
-// staged in LDS by wavefront 0 (all written by earlier launches).
-struct FinScalars {
-  double alpha[kMaxM];
-  double offd[kMaxM];
-  double scale[kMaxM];
-  cplx_d coef[kMaxM];    // step k-1's projection coefficients (window order)
-  cplx_d gprev[kMaxM];   // the Gram column measured two steps back
-  cplx_d cdiag[kMaxM];
-  cplx_d csub[kMaxM];
-  double normT, beta0;
-};
-
 // One lane's share of FinScalars.  Plain doubles, assigned one by one, so that
 // they stay in registers while the loads are in flight.
 struct FinRegs {
@@ -352,85 +339,6 @@ __device__ __forceinline__ void store_y(const Tile<R, RB>& T, typename VT<R>::T*
       yk[s] = o;
     }
   }
-}
-
-// The window dots of step k, d_i = <u_i|H u_k> for i in [i0, k), on wavefront
-// 0 (lane l: i = i0 + l), without reading a window vector.  u_i are the stored
-// (unnormalised) vectors, s_i = 1/||u_i|| and c^(i) the projection
-// coefficients of step i, so that pass B(i) stored
-//   u_{i+1} = s_i y_i - sum_j c^(i)_j u_j,   y_i = H u_i.
-// As H is Hermitian, d_i = <y_i|u_k> = (e_{i+1} + sum_j conj(c^(i)_j) e_j) / s_i
-// with e_j = <u_j|u_k>; and with p = k-1,
-//   e_j = s_p <u_j|y_p> - sum_l c^(p)_l G_jl,   e_k = ||u_k||^2,
-// where G_jl = <u_j|u_l>.  Pass B(p) measured <u_j|y_p> (columns [0, nb)) and
-// G_jp (columns [nb, 2nb)) on the stored vectors, and pass B(p-1) the column
-// G_{j,p-1}.  In a re-orthogonalised basis the entries G_jl (j != l) and the
-// coefficients c^(i)_j (j < i-1) are of the order of the rounding error, so
-// the products of two of them are dropped: the sums keep l in {j, p-1, p} and
-// j in {i-1, i}, which are all the terms of the three-term window.  In exact
-// arithmetic the dots are exact either way (G is then diagonal).  With
-// `writer` the measured column G_jp is kept in the state for step k+1.
-__device__ cplx_d window_dots(const LzArgs& a, const FinScalars& fs, const cplx_d* tot, int nb,
-                             double ekk, bool writer) {
-  KState* st = a.st;
-  const int lane = threadIdx.x & 63;
-  const int p = a.k - 1, ip = a.i0p;
-  const int j = ip + lane;
-  const bool has_pm = p - 1 >= ip;
-  // step p's coefficients and the stored scalars
-  const cplx_d cp = fs.coef[p - ip];
-  const cplx_d cpm = has_pm ? fs.coef[p - 1 - ip] : cplx_d{0.0, 0.0};
-  const double sp = fs.scale[p];
-  double er = 0.0, ei = 0.0;
-  if (lane < nb) {
-    const cplx_d cj = fs.coef[lane];
-    const double sj = fs.scale[j];
-    const cplx_d gjp = tot[nb + lane];
-    cplx_d gjm{0.0, 0.0};   // G_{j,p-1}
-    if (has_pm) {
-      if (j == p) {
-        gjm = tot[nb + (p - 1 - ip)];
-        gjm.im = -gjm.im;
-      } else if (j == p - 1) {
-        gjm = cplx_d{1.0 / (sj * sj), 0.0};
-      } else {
-        gjm = fs.gprev[j];   // gcol[(p - 1) & 1], staged
-      }
-    }
-    er = sp * tot[lane].re - (cp.re * gjp.re - cp.im * gjp.im) -
-         (cpm.re * gjm.re - cpm.im * gjm.im);
-    ei = sp * tot[lane].im - (cp.re * gjp.im + cp.im * gjp.re) -
-         (cpm.re * gjm.im + cpm.im * gjm.re);
-    if (j < p - 1) {
-      const double gjj = 1.0 / (sj * sj);
-      er -= cj.re * gjj;
-      ei -= cj.im * gjj;
-    }
-    if (writer) st->gcol[p & 1][j] = gjp;   // for step k+1
-  } else if (lane == nb) {
-    er = ekk;   // j = k
-  }
-  // lane l: i = i0 + l takes e_{i+1}, e_i and e_{i-1} from lanes i+1-ip, i-ip, i-1-ip
-  const int i = a.i0 + lane;
-  const bool want = i < a.k;
-  const int src = i - ip;
-  const double e1r = __shfl(er, min(max(src + 1, 0), 63), 64);
-  const double e1i = __shfl(ei, min(max(src + 1, 0), 63), 64);
-  const double e0r = __shfl(er, min(max(src, 0), 63), 64);
-  const double e0i = __shfl(ei, min(max(src, 0), 63), 64);
-  const double emr = __shfl(er, min(max(src - 1, 0), 63), 64);
-  const double emi = __shfl(ei, min(max(src - 1, 0), 63), 64);
-  if (!want) return cplx_d{0.0, 0.0};
-  const cplx_d cd = fs.cdiag[i];
-  double dr = e1r + cd.re * e0r + cd.im * e0i;
-  double di = e1i + cd.re * e0i - cd.im * e0r;
-  if (i >= 1 && i - 1 >= ip) {
-    const cplx_d cs = fs.csub[i];
-    dr += cs.re * emr + cs.im * emi;
-    di += cs.re * emi - cs.im * emr;
-  }
-  const double si = fs.scale[i];
-  return cplx_d{dr / si, di / si};
 }
 
 // The reduced sums of step k into `tot` (LDS) and the earlier steps' scalars
@@ -550,7 +458,9 @@ __device__ bool step_update(const LzArgs& a, const FinScalars& fs, const cplx_d*
     }
   }
   // lane l: window index i0 + l (a window holds at most kMaxM <= 64 vectors)
-  const cplx_d d = (nb > 0) ? window_dots(a, fs, tot, nb, tot[ns].re, writer) : cplx_d{0.0, 0.0};
+  const cplx_d d = (nb > 0) ? window_dots(k, a.i0, a.i0p, fs, tot, nb, tot[ns].re,
+                                          writer ? st->gcol[(k - 1) & 1] : nullptr)
+                             : cplx_d{0.0, 0.0};
   if (lane < nwin) {
     const int i = a.i0 + lane;
     const double si = (i == k) ? sk : fs.scale[i];
