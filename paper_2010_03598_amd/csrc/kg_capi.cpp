@@ -524,22 +524,24 @@ size_t ws_fixed_bytes() {
 }
 
 // Tile of a standalone H v (xxz_apply), from graph-timed launches at
-// L = 12..24 over tiles of 2^8..2^12: small tiles (more blocks per compute
+// L = 12..24 over tiles of 2^8..2^13: small tiles (more blocks per compute
 // unit to hide the partner loads) up to L = 18, larger ones as the vector
-// outgrows the caches.  The Krylov passes keep make_geo's tiles, which were
-// timed as whole Krylov calls.
+// outgrows the caches (complex64 in the pair layout from 2^10).  The Krylov
+// passes keep make_geo's tiles, which were timed as whole Krylov calls.
 int hv_tile_bits(int L, int prec) {
   if (L <= 18) return 8;
   if (prec == KG_C128) return (L <= 20) ? 9 : (L <= 22 ? 11 : 12);
   return (L <= 21) ? 10 : (L == 22 ? 11 : 12);
 }
 
-Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap) {
+Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap, bool standalone) {
   Geo g;
   memset(&g, 0, sizeof(g));
   g.L = L;
   g.D = 1u << L;
-  const int tb_max = 12;
+  // complex64 tiles of 2^13 (eight amplitudes per thread, 1024 threads) only
+  // for the standalone H v: the Lanczos passes keep at most 2^12
+  const int tb_max = (standalone && prec == KG_C64) ? 13 : 12;
   // default tile, from Krylov-call timings at L = 16..26: 2^9..2^11
   // amplitudes up to L = 18 (complex64) or L = 19 (complex128), the largest
   // tile beyond; complex64 vectors of 2^23 amplitudes and more go back to
@@ -556,8 +558,8 @@ Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap) {
   if (tb < 6) tb = 6;
   // amplitudes per thread (2^RB) grow with the tile until register pressure
   // limits them; the rest of the tile is spread over up to 16 wavefronts
-  static const int rb_c64[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2};
-  static const int rb_c128[13] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 3};
+  static const int rb_c64[14] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 2, 3};
+  static const int rb_c128[14] = {0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 2, 2, 3, 3};
   g.TB = tb;
   g.RB = (prec == KG_C128) ? rb_c128[tb] : rb_c64[tb];
   g.WB = tb - 6 - g.RB;
@@ -604,7 +606,8 @@ kg_status xxz_apply(const kg_xxz* h, double u, int32_t prec, const void* v, void
   KG_CHECK(check_vec(w, prec, "w"));
   if (overlap(v, w, vec_bytes(h->L, prec))) return fail(KG_EINVAL, "v and w overlap");
   const int tb_env = tile_override_from_env();
-  const Geo g = make_geo(h->L, prec, tb_env >= 6 ? tb_env : hv_tile_bits(h->L, prec), kMaxGrid);
+  const Geo g = make_geo(h->L, prec, tb_env >= 6 ? tb_env : hv_tile_bits(h->L, prec), kMaxGrid,
+                         true);
   const HvArgs a = make_hv(h, nullptr, u);
   Profiler* prof = profiler_for_launch();
   if (prof) profiler_start(prof, (hipStream_t)stream);

@@ -747,6 +747,172 @@ __device__ __forceinline__ void hv_tile(Tile<R, RB>& T, const HvArgs& a, const G
 
 }
 
+// y = (H0 + u Hc) x on one full tile of complex64 amplitudes held in pairs, so
+// that every global and LDS access moves 16 bytes: thread (lane, w) holds the
+// pairs q in [0, 2^(RB-1)) with amplitudes
+//   e = h | lane << 1 | q << 7 | w << (6+RB),   h = 0, 1.
+// Bonds with a bit below 6+RB (inside the wavefront) and the active bonds
+// between two wavefront bits read the partner pair from LDS; bonds reaching
+// the tile-index bits read the partner tile's pairs from global memory (a
+// predicate uniform over the wavefront), as hv_tile does.  A partner e ^ (3 << p)
+// is in the same half of a pair unless p = 0 (bits 0 and 1), where it is the
+// other half of the neighbouring pair.  Needs RB >= 2, 2^TB <= D and at least
+// two wavefronts (6+RB < TB), and 16-byte aligned x.
+template <int RB, bool kCoh = false>
+__device__ __forceinline__ void hv_tile_pairs(Tile<float, RB>& T, const HvArgs& a, const Geo& g,
+                                              uint32_t tile, const float2* __restrict__ x,
+                                              float2* lds, double u) {
+  static_assert(RB >= 2, "two pairs or more per thread");
+  constexpr int NR = 1 << RB;
+  constexpr int NP = NR / 2;
+  constexpr int NS = FarSlots<float, RB>::n;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t w = uniform_u32(threadIdx.x >> 6);
+  const int L = g.L;
+  const int TB = g.TB;
+  const uint32_t base = tile << TB;
+  const uint32_t wb = w << (6 + RB);
+  const uint32_t bondmask = (1u << (L - 1)) - 1u;
+  const float hJ = (float)a.half_J;
+  const float cu = (float)(0.5 * u);
+  const float4* __restrict__ x4 = reinterpret_cast<const float4*>(x);
+  float4* lds4 = reinterpret_cast<float4*>(lds);
+  uint32_t ep[NP];   // first amplitude of pair q inside the tile
+#pragma unroll
+  for (int q = 0; q < NP; ++q) ep[q] = (lane << 1) | ((uint32_t)q << 7) | wb;
+
+  // bonds between two wavefront or tile bits (p >= 6+RB): wavefront-uniform
+  const int p0 = 6 + RB;
+  const uint32_t sU = base | wb;
+  uint32_t act = (sU ^ (sU >> 1)) & bondmask;
+  act = (act >> p0) << p0;
+  const uint32_t lds_bonds = act & ((1u << (TB - 1)) - 1u);
+  uint32_t glb = act & ~lds_bonds;
+  const bool sx_glb = (a.hc_kind == 0) && (a.hc_bit >= TB);
+
+  // ---- round trip 1: own pairs, the S^x partner and the first far partners
+  float4 own[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) own[q] = x4[(base | ep[q]) >> 1];
+  uint32_t f[NS];
+  float cf[NS];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+    if (j == 0 && sx_glb) {
+      f[0] = 1u << a.hc_bit;
+      cf[0] = cu;
+    } else {
+      next_far<float>(glb, hJ, f[j], cf[j]);
+    }
+  }
+  float4 gq[NS][NP];
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) gq[j][q] = ld_partner<kCoh>(&x4[((base | ep[q]) ^ f[j]) >> 1]);
+  }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    lds4[ep[q] >> 1] = own[q];
+    T.xr[2 * q] = own[q].x;
+    T.xi[2 * q] = own[q].y;
+    T.xr[2 * q + 1] = own[q].z;
+    T.xi[2 * q + 1] = own[q].w;
+  }
+  __syncthreads();
+
+  // ---- diagonal: J Delta/4 (L-1-2 n_anti) (+ u sum_{i in A}(1/2 - b_i) for S^z)
+  const float czz = (float)a.c_zz;
+  const float uR = (float)u;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const uint32_t s = base | ep[r >> 1] | (uint32_t)(r & 1);
+    const int n = __popc((s ^ (s >> 1)) & bondmask);
+    float d = czz * (float)(L - 1 - 2 * n);
+    if (a.hc_kind == 1) d += uR * ((float)(0.5 * a.sz_count) - (float)__popc(s & a.sz_mask));
+    T.yr[r] = d * T.xr[r];
+    T.yi[r] = d * T.xi[r];
+  }
+
+  // ---- bonds inside the tile: the partner pair from LDS
+  uint32_t inb = ((1u << p0) - 1u) | lds_bonds;
+  while (inb) {
+    const int p = __builtin_ctz(inb);
+    inb &= inb - 1;
+    const uint32_t flip = 3u << p;
+    float4 P[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) P[q] = lds4[(ep[q] ^ flip) >> 1];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t e = ep[q] | (uint32_t)h;
+        const float c = (((e >> p) ^ (e >> (p + 1))) & 1u) ? hJ : 0.0f;
+        const bool other = (p == 0) ? (h == 0) : (h == 1);   // the partner's half
+        const float pr = other ? P[q].z : P[q].x;
+        const float pi = other ? P[q].w : P[q].y;
+        T.yr[2 * q + h] += c * pr;
+        T.yi[2 * q + h] += c * pi;
+      }
+    }
+  }
+
+  // ---- far partners of round trip 1, then the remaining far bonds NS per round trip
+#pragma unroll
+  for (int j = 0; j < NS; ++j) {
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      T.yr[2 * q] += cf[j] * gq[j][q].x;
+      T.yi[2 * q] += cf[j] * gq[j][q].y;
+      T.yr[2 * q + 1] += cf[j] * gq[j][q].z;
+      T.yi[2 * q + 1] += cf[j] * gq[j][q].w;
+    }
+  }
+  while (glb) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) next_far<float>(glb, hJ, f[j], cf[j]);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) gq[j][q] = ld_partner<kCoh>(&x4[((base | ep[q]) ^ f[j]) >> 1]);
+    }
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        T.yr[2 * q] += cf[j] * gq[j][q].x;
+        T.yi[2 * q] += cf[j] * gq[j][q].y;
+        T.yr[2 * q + 1] += cf[j] * gq[j][q].z;
+        T.yi[2 * q + 1] += cf[j] * gq[j][q].w;
+      }
+    }
+  }
+
+  // ---- S^x control inside the tile: u/2 times the amplitude with that bit flipped
+  if (a.hc_kind == 0 && !sx_glb) {
+    const uint32_t flip = 1u << a.hc_bit;
+    float4 P[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) P[q] = lds4[(ep[q] ^ flip) >> 1];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const bool other = (flip & 1u) ? (h == 0) : (h == 1);
+        T.yr[2 * q + h] += cu * (other ? P[q].z : P[q].x);
+        T.yi[2 * q + h] += cu * (other ? P[q].w : P[q].y);
+      }
+    }
+  }
+}
+
+// Whether a tiling of complex64 amplitudes runs hv_tile_pairs: whole tiles of
+// at least two wavefronts with two pairs or more per thread.
+__host__ __device__ inline bool pairs_tiling(const Geo& g) {
+  return !g.small && g.RB >= 2 && g.TB > 6 + g.RB;
+}
+
 __device__ __forceinline__ double control_value(const HvArgs& a) {
   return a.u_ptr ? *a.u_ptr : a.u_val;
 }

@@ -77,8 +77,10 @@ struct Geo {               // tiling of one state vector
 };
 
 // Tiling of a 2^L vector; grid_cap bounds the grid (kLzGrid for the Lanczos
-// passes, kMaxGrid for a standalone H v).
-Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap = kLzGrid);
+// passes, kMaxGrid for a standalone H v); `standalone` allows the larger
+// complex64 tile of the standalone H v.
+Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap = kLzGrid,
+             bool standalone = false);
 int stream_grid(uint32_t D);
 
 struct Workspace {         // carved from the caller's workspace

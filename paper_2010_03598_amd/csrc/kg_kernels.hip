@@ -60,8 +60,22 @@ namespace {
 
 // ---------------------------------------------------------------------- xxz_apply
 
-template <typename R, int RB>
-__global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_hv(HvArgs a, Geo g, const typename VT<R>::T* __restrict__ v,
+// Store y of a pair-layout tile (hv_tile_pairs): 16 bytes per pair.
+template <int RB>
+__device__ __forceinline__ void store_pairs(const Tile<float, RB>& T, float2* out, uint32_t base) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wb = uniform_u32(threadIdx.x >> 6) << (6 + RB);
+#pragma unroll
+  for (int q = 0; q < (1 << RB) / 2; ++q) {
+    const uint32_t e = (lane << 1) | ((uint32_t)q << 7) | wb;
+    reinterpret_cast<float4*>(out)[(base | e) >> 1] =
+        float4{T.yr[2 * q], T.yi[2 * q], T.yr[2 * q + 1], T.yi[2 * q + 1]};
+  }
+}
+
+// kPairs: complex64 in the pair layout (hv_tile_pairs), 16-byte accesses.
+template <typename R, int RB, bool kPairs = false>
+__global__ void __launch_bounds__((RB >= 3 && sizeof(R) == 8) ? 512 : 1024) k_hv(HvArgs a, Geo g, const typename VT<R>::T* __restrict__ v,
                                             typename VT<R>::T* __restrict__ w) {
   using V = typename VT<R>::T;
   extern __shared__ unsigned char smem_raw[];
@@ -75,8 +89,13 @@ __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_hv(HvArgs a, Geo g, co
   for (uint32_t it = 0; it < iters; ++it) {
     const uint32_t tile = tile_of(g, it, blockIdx.x, gridDim.x);
     if (it) __syncthreads();
-    hv_tile<R, RB>(T, a, g, tile, v, lds, u);
     const uint32_t base = tile << g.TB;
+    if constexpr (kPairs) {
+      hv_tile_pairs<RB>(T, a, g, tile, v, lds, u);
+      store_pairs<RB>(T, w, base);
+      continue;
+    }
+    hv_tile<R, RB>(T, a, g, tile, v, lds, u);
 #pragma unroll
     for (int r = 0; r < (1 << RB); ++r) {
       const uint32_t s = base | eb | ((uint32_t)r << 6);
@@ -499,7 +518,7 @@ __device__ bool step_update(const LzArgs& a, const FinScalars& fs, const cplx_d*
 // 2nb + 1 totals instead of the whole table.
 // kYIn: y_k was written by a separate H v kernel (the reduced basis); the pass
 // then loads it instead of forming it on the tile.
-template <typename R, int RB, bool kYIn = false>
+template <typename R, int RB, bool kYIn = false, bool kPairs = false>
 __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
@@ -538,6 +557,9 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
         T.yr[r] = yy.x;
         T.yi[r] = yy.y;
       }
+    } else if constexpr (kPairs) {
+      hv_tile_pairs<RB>(T, a.hv, a.geo, tile, x, lds, u);
+      if (a.k + 1 < a.m) store_pairs<RB>(T, yk, base);
     } else {
       hv_tile<R, RB>(T, a.hv, a.geo, tile, x, lds, u);
       if (a.k + 1 < a.m) store_y<R, RB>(T, yk, base, eb, a.geo);
@@ -577,13 +599,13 @@ __device__ __forceinline__ void pass_a_body(const LzArgs& a, uint32_t bl, uint32
   }
 }
 
-template <typename R, int RB>
+template <typename R, int RB, bool kPairs = false>
 __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_a(LzBatch B) {
   const uint32_t G = B.job[0].geo.grid;
   if (blockIdx.x < G) {
-    pass_a_body<R, RB>(B.job[0], blockIdx.x, G);
+    pass_a_body<R, RB, false, kPairs>(B.job[0], blockIdx.x, G);
   } else {
-    pass_a_body<R, RB>(B.job[1], blockIdx.x - G, G);
+    pass_a_body<R, RB, false, kPairs>(B.job[1], blockIdx.x - G, G);
   }
 }
 
@@ -1124,6 +1146,16 @@ size_t lds_bytes(const Geo& g) {
 template <typename R, int RB>
 hipError_t launch_hv_t(const HvArgs& a, const Geo& g, const void* v, void* w, hipStream_t s) {
   using V = typename VT<R>::T;
+  // complex64 whole tiles in pairs when both vectors are 16-byte aligned
+  const bool pairs = sizeof(R) == 4 && RB >= 2 && pairs_tiling(g) &&
+                     (((uintptr_t)v | (uintptr_t)w) % 16) == 0;
+  if constexpr (sizeof(R) == 4 && RB >= 2) {
+    if (pairs) {
+      hipLaunchKernelGGL((k_hv<R, RB, true>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, a,
+                         g, reinterpret_cast<const V*>(v), reinterpret_cast<V*>(w));
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((k_hv<R, RB>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, a, g,
                      reinterpret_cast<const V*>(v), reinterpret_cast<V*>(w));
   return hipGetLastError();
@@ -1156,6 +1188,17 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
   const Geo& g = lb.job[0].geo;
   const dim3 grid(g.grid * njobs), block(64 << g.WB);
   if (pass_a) {
+    bool pairs = sizeof(R) == 4 && RB >= 2 && pairs_tiling(g);
+    for (int j = 0; j < njobs; ++j) {
+      const LzArgs& q = lb.job[j];
+      if (((uintptr_t)q.slot0 | (uintptr_t)q.basis | (uintptr_t)q.yk) % 16) pairs = false;
+    }
+    if constexpr (sizeof(R) == 4 && RB >= 2) {
+      if (pairs) {
+        hipLaunchKernelGGL((k_pass_a<R, RB, true>), grid, block, lds_bytes<R>(g), s, lb);
+        return hipGetLastError();
+      }
+    }
     hipLaunchKernelGGL((k_pass_a<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
   } else {
     const size_t red = ((size_t)1 << g.WB) * kMaxScal * sizeof(cplx_d);

@@ -114,14 +114,18 @@ def test_random_vectors_c64(L):
     assert np.abs(out - ref).max() <= 2e-6 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("tb", [6, 7, 8, 9, 10, 11, 12])
+@pytest.mark.parametrize("tb", [6, 7, 8, 9, 10, 11, 12, 13])
 @pytest.mark.parametrize("dtype", [C128, C64])
 def test_every_tiling(tb, dtype):
-    """Every (register, wavefront) split of the tile gives the same H v."""
+    """Every (register, wavefront) split of the tile gives the same H v, for
+    complex64 also the pair layout (tiles of 2^10 and more); S^x on the first
+    site (a far partner), on site 11 (inside the wavefront) and on the last site
+    (the other half of the thread's own pair in the pair layout)."""
     L = 14
     rng = np.random.default_rng(tb)
     v = workloads.random_state(rng, 1 << L)
-    for kind, sites in [(HC_SX, 1), (HC_SX, 1 << 10), (HC_SZ, 0b101 << 5)]:
+    for kind, sites in [(HC_SX, 1), (HC_SX, 1 << 10), (HC_SX, 1 << (L - 1)),
+                        (HC_SZ, 0b101 << 5)]:
         ref = model.apply_h(L, 1.0, 0.8, kind, sites, 0.45, v.astype(dtype_np(dtype)).astype(complex))
         with tile_bits(tb):
             out = host(kg.xxz_apply(kg.XXZ(L, 1.0, 0.8, kind, sites), 0.45, dev_vec(v, dtype)))
