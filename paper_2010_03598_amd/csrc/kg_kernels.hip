@@ -51,6 +51,9 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#include <stdlib.h>
+
+#include <atomic>
 
 #include "kg_device.h"
 #include "kg_internal.h"
@@ -128,6 +131,58 @@ __global__ void __launch_bounds__((RB >= 3 && sizeof(R) == 8) ? 512 : 1024) k_hv
 // binomial table is staged in LDS; the label's own rank comes from the tables.
 constexpr int kPeHops = 8;
 
+// One output of the reduced-basis H v: row b, with the binomials in LDS (sb)
+// and xat(i) the amplitude of orbit i.  Sets `bad` when a table entry is out
+// of range (the output is then NaN, never a stray load).
+template <typename R, typename XAt>
+__device__ __forceinline__ void pe_row(const HvArgs& a, const PeArgs& p, const uint32_t* sb, double u,
+                                       uint32_t b, XAt xat, R& yr, R& yi, bool& bad) {
+  using V = typename VT<R>::T;
+  const int L = p.L;
+  const uint32_t full = (L == 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+  const uint32_t bondmask = (L >= 2) ? ((1u << (L - 1)) - 1u) : 0u;
+  const R hJ = (R)a.half_J, czz = (R)a.c_zz, uR = (R)u;
+  const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
+  const uint32_t r = p.reps[b];
+  const uint32_t rank = p.ranks[b];
+  const uint32_t zeros = ~r & full;
+  const bool nb2 = (__brev(r) >> (32 - L)) != r;
+  const int n_anti = (int)__popc((r ^ (r >> 1)) & bondmask);   // __popc is unsigned
+  R d = czz * (R)(L - 1 - 2 * n_anti);
+  if (a.hc_kind == 1) d += uR * ((R)(0.5 * a.sz_count) - (R)__popc(r & a.sz_mask));
+  const V xb = xat(b);
+  yr = d * xb.x;
+  yi = d * xb.y;
+  bad = rank >= p.nsec;
+  uint32_t act = bad ? 0u : ((r ^ (r >> 1)) & bondmask);
+  while (act) {
+    uint32_t rk[kPeHops];
+    R w[kPeHops];
+#pragma unroll
+    for (int j = 0; j < kPeHops; ++j) {
+      const bool on = act != 0u;
+      const int q = on ? __builtin_ctz(act) : 0;
+      act &= act - 1u;
+      const uint32_t dl = sb[q * kPeBinom + __popc(zeros & ((1u << q) - 1u))];
+      const uint32_t s2 = r ^ (3u << q);
+      const bool na2 = (__brev(s2) >> (32 - L)) != s2;
+      rk[j] = on ? ((((r >> q) & 1u) == 0u) ? rank + dl : rank - dl) : rank;
+      w[j] = on ? ((nb2 == na2) ? (R)1 : (nb2 ? rt2 : irt2)) : (R)0;
+    }
+    int32_t ai[kPeHops];
+#pragma unroll
+    for (int j = 0; j < kPeHops; ++j) ai[j] = (rk[j] < p.nsec) ? p.index[rk[j]] : -1;
+#pragma unroll
+    for (int j = 0; j < kPeHops; ++j) {
+      const bool ok = (uint32_t)ai[j] < p.dim;
+      bad = bad || !ok;
+      const V xa = xat(ok ? (uint32_t)ai[j] : b);
+      yr += hJ * w[j] * xa.x;
+      yi += hJ * w[j] * xa.y;
+    }
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_hv_pe(HvArgs a, PeArgs p,
                                                const typename VT<R>::T* __restrict__ x,
@@ -136,12 +191,7 @@ __global__ void __launch_bounds__(256) k_hv_pe(HvArgs a, PeArgs p,
   __shared__ uint32_t sb[kPeBinom * kPeBinom];
   for (int i = threadIdx.x; i < kPeBinom * kPeBinom; i += blockDim.x) sb[i] = p.binom[i];
   __syncthreads();
-  const int L = p.L;
-  const uint32_t full = (L == 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
-  const uint32_t bondmask = (L >= 2) ? ((1u << (L - 1)) - 1u) : 0u;
   const double u = control_value(a);
-  const R hJ = (R)a.half_J, czz = (R)a.c_zz, uR = (R)u;
-  const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
   uint32_t lo = 0, hi = p.dim, b0 = blockIdx.x * blockDim.x + threadIdx.x,
            stride = gridDim.x * blockDim.x;
   if ((gridDim.x & 7u) == 0u) {
@@ -153,44 +203,9 @@ __global__ void __launch_bounds__(256) k_hv_pe(HvArgs a, PeArgs p,
     stride = (gridDim.x >> 3) * blockDim.x;
   }
   for (uint32_t b = b0; b < hi; b += stride) {
-    const uint32_t r = p.reps[b];
-    const uint32_t rank = p.ranks[b];
-    const uint32_t zeros = ~r & full;
-    const bool nb2 = (__brev(r) >> (32 - L)) != r;
-    const int n_anti = (int)__popc((r ^ (r >> 1)) & bondmask);   // __popc is unsigned
-    R d = czz * (R)(L - 1 - 2 * n_anti);
-    if (a.hc_kind == 1) d += uR * ((R)(0.5 * a.sz_count) - (R)__popc(r & a.sz_mask));
-    const V xb = x[b];
-    R yr = d * xb.x, yi = d * xb.y;
-    bool bad = rank >= p.nsec;
-    uint32_t act = bad ? 0u : ((r ^ (r >> 1)) & bondmask);
-    while (act) {
-      uint32_t rk[kPeHops];
-      R w[kPeHops];
-#pragma unroll
-      for (int j = 0; j < kPeHops; ++j) {
-        const bool on = act != 0u;
-        const int q = on ? __builtin_ctz(act) : 0;
-        act &= act - 1u;
-        const uint32_t dl = sb[q * kPeBinom + __popc(zeros & ((1u << q) - 1u))];
-        const uint32_t s2 = r ^ (3u << q);
-        const bool na2 = (__brev(s2) >> (32 - L)) != s2;
-        rk[j] = on ? ((((r >> q) & 1u) == 0u) ? rank + dl : rank - dl) : rank;
-        w[j] = on ? ((nb2 == na2) ? (R)1 : (nb2 ? rt2 : irt2)) : (R)0;
-      }
-      int32_t ai[kPeHops];
-#pragma unroll
-      for (int j = 0; j < kPeHops; ++j) ai[j] = (rk[j] < p.nsec) ? p.index[rk[j]] : -1;
-      // tables live in caller memory: an entry out of range gives NaN, never a stray load
-#pragma unroll
-      for (int j = 0; j < kPeHops; ++j) {
-        const bool ok = (uint32_t)ai[j] < p.dim;
-        bad = bad || !ok;
-        const V xa = x[ok ? (uint32_t)ai[j] : b];
-        yr += hJ * w[j] * xa.x;
-        yi += hJ * w[j] * xa.y;
-      }
-    }
+    R yr, yi;
+    bool bad;
+    pe_row<R>(a, p, sb, u, b, [&](uint32_t i) { return x[i]; }, yr, yi, bad);
     V o;
     o.x = bad ? (R)NAN : yr;
     o.y = bad ? (R)NAN : yi;
@@ -1165,7 +1180,9 @@ template <typename R>
 hipError_t launch_hv_pe_t(const HvArgs& a, const PeArgs& p, const void* v, void* w, hipStream_t s) {
   using V = typename VT<R>::T;
   uint32_t blocks = (p.dim + 255u) / 256u;
-  if (blocks > 2048u) blocks = 2048u;   // grid-stride beyond (the binomials are staged per block)
+  // grid-stride beyond 8192 blocks (the binomials are staged per block); at
+  // 2.6 million rows 8192 blocks were 6 % faster than 2048
+  if (blocks > 8192u) blocks = 8192u;
   if (blocks < 1u) blocks = 1u;
   if (blocks >= 64u) blocks = (blocks + 7u) & ~7u;
   hipLaunchKernelGGL((k_hv_pe<R>), dim3(blocks), dim3(256), 0, s, a, p, reinterpret_cast<const V*>(v),
@@ -1234,10 +1251,324 @@ hipError_t launch_pass_r(bool pass_a, const LzBatch& lb, int njobs, hipStream_t 
 
 // Advance n (1 or 2) independent Krylov calls of one shape (same L, m,
 // reorth, precision) through the same launches.
+// ---------------------------------------------------------------------- one-block Krylov call
+
+// A whole Krylov call (Algorithm 2, the small exponential of Eqs. A2-A3 and
+// the combination) by one block, for vectors whose stored basis fits in LDS:
+// D <= kFusedMaxD amplitudes and m D amplitudes of LDS at most kFusedLds
+// bytes.  At such sizes the tiled form is a chain of about 2m dependent
+// launches of one block each, bound by their latency; here the basis never
+// leaves LDS and a step costs a few block barriers.
+//
+// Thread t owns amplitudes (rows) t + kFusedBlock a.  The stored vectors
+// are u_0 = the input as given and u_{k+1} = w_{k+1} rounded to the vector
+// type, unnormalised, with their scales s_k = 1/||u_k|| kept in FP64; step k
+// forms y = s_k H u_k (accumulated in the vector type, as the tiled H v),
+// takes the projection coefficients c_i = s_i <u_i|y> against the same y
+// over the window (classical Gram-Schmidt: every stored vector with full
+// re-orthonormalisation, the last two without), alpha_k = s_k Re<u_k|y>, and
+// w = y - sum_i c_i s_i u_i in FP64.  The breakdown test and the combination
+// are those of the tiled passes.  Reductions: quad_sums within a wavefront,
+// then the wavefronts in order, so every thread reads the same totals.
+constexpr int kFusedBlock = 256;
+constexpr int kFusedNA = 4;                                   // amplitudes per thread
+constexpr uint32_t kFusedMaxD = kFusedBlock * kFusedNA;
+constexpr size_t kFusedLds = (size_t)120 << 10;               // bytes of stored vectors
+constexpr int kFusedRed = 2 * kMaxM + 4;
+
+struct FusedJob {
+  HvArgs hv;
+  PeArgs pe;
+  int32_t has_pe;
+  uint32_t D;
+  int32_t m, reorth;
+  double t, tol;
+  const void* v_in;
+  void* v_out;
+  int32_t* m_eff_out;
+};
+
+struct FusedBatch {
+  FusedJob job[kMaxJobs];
+};
+
+// Row s of (H0 + u Hc) x on the full 2^L space, x in LDS (as hv_tile, one row).
+template <typename R>
+__device__ __forceinline__ void full_row(const HvArgs& a, uint32_t s, const typename VT<R>::T* x,
+                                         double u, R& yr, R& yi) {
+  using V = typename VT<R>::T;
+  const int L = a.L;
+  const uint32_t bondmask = (L >= 2) ? ((1u << (L - 1)) - 1u) : 0u;
+  const uint32_t act = (s ^ (s >> 1)) & bondmask;
+  const int n_anti = (int)__popc(act);   // __popc is unsigned
+  R d = (R)a.c_zz * (R)(L - 1 - 2 * n_anti);
+  if (a.hc_kind == 1) d += (R)u * ((R)(0.5 * a.sz_count) - (R)__popc(s & a.sz_mask));
+  const V xs = x[s];
+  yr = d * xs.x;
+  yi = d * xs.y;
+  const R hJ = (R)a.half_J;
+  for (uint32_t b = act; b; b &= b - 1u) {
+    const V q = x[s ^ (3u << __builtin_ctz(b))];
+    yr += hJ * q.x;
+    yi += hJ * q.y;
+  }
+  if (a.hc_kind == 0) {
+    const R cu = (R)(0.5 * u);
+    const V q = x[s ^ (1u << a.hc_bit)];
+    yr += cu * q.x;
+    yi += cu * q.y;
+  }
+}
+
+// Totals of n <= kFusedRed values that every wavefront has put in wred[w][0, n):
+// tot[j] = sum over the wavefronts in order.  Barriers before and after.
+__device__ __forceinline__ void fused_totals(double (*wred)[kFusedRed], int n, double* tot) {
+  __syncthreads();
+  for (int j = threadIdx.x; j < n; j += blockDim.x) {
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < kFusedBlock / 64; ++w) v += wred[w][j];
+    tot[j] = v;
+  }
+  __syncthreads();
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kFusedBlock) k_krylov_fused(FusedBatch B) {
+  using V = typename VT<R>::T;
+  const FusedJob& J = B.job[blockIdx.x];
+  extern __shared__ unsigned char smem_raw[];
+  V* ub = reinterpret_cast<V*>(smem_raw);   // stored vectors, [m][D]
+  __shared__ double wred[kFusedBlock / 64][kFusedRed];
+  __shared__ double tot[kFusedRed];
+  __shared__ double sc[kMaxM + 1], al[kMaxM], off[kMaxM + 1];
+  __shared__ cplx_d dco[kMaxM];
+  __shared__ uint32_t sb[kPeBinom * kPeBinom];
+
+  const int tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t wv = uniform_u32(tid >> 6);
+  const uint32_t D = J.D;
+  const int m = J.m;
+  const V* __restrict__ vin = reinterpret_cast<const V*>(J.v_in);
+  V* __restrict__ vout = reinterpret_cast<V*>(J.v_out);
+  const double u = control_value(J.hv);
+  if (J.has_pe)
+    for (int i = tid; i < kPeBinom * kPeBinom; i += kFusedBlock) sb[i] = J.pe.binom[i];
+
+  // u_0 = the input; beta0 = ||u_0||
+  double nn = 0.0;
+#pragma unroll
+  for (int q = 0; q < kFusedNA; ++q) {
+    const uint32_t s = tid + kFusedBlock * q;
+    if (s < D) {
+      const V v = vin[s];
+      ub[s] = v;
+      nn += (double)v.x * v.x + (double)v.y * v.y;
+    }
+  }
+  nn = wave_sum(nn);
+  if (lane == 0) wred[wv][0] = nn;
+  fused_totals(wred, 1, tot);
+  const double b0sq = tot[0];
+  if (!(b0sq > 0.0)) {
+    // a zero input gives a zero output; a non-finite one a NaN output
+    const bool zero = b0sq == 0.0;
+#pragma unroll
+    for (int q = 0; q < kFusedNA; ++q) {
+      const uint32_t s = tid + kFusedBlock * q;
+      if (s < D) vout[s] = zero ? V{(R)0, (R)0} : V{(R)NAN, (R)NAN};
+    }
+    if (tid == 0 && J.m_eff_out) *J.m_eff_out = zero ? 0 : 1;
+    return;
+  }
+  const double beta0 = sqrt(b0sq);
+  if (tid == 0) {
+    sc[0] = 1.0 / beta0;
+    off[0] = 0.0;
+  }
+  __syncthreads();
+
+  double normT = 0.0;
+  int meff = m;
+  for (int k = 0; k < m; ++k) {
+    const bool last = k == m - 1;
+    const int i0 = last ? k : (J.reorth ? 0 : (k > 0 ? k - 1 : 0));
+    const int nw = k - i0 + 1;
+    const double sk = sc[k];
+    const V* uk = ub + (size_t)k * D;
+    // y = s_k H u_k on this thread's rows
+    double yr[kFusedNA], yi[kFusedNA];
+#pragma unroll
+    for (int q = 0; q < kFusedNA; ++q) {
+      const uint32_t s = tid + kFusedBlock * q;
+      R hr = (R)0, hi = (R)0;
+      if (s < D) {
+        if (J.has_pe) {
+          bool bad;
+          pe_row<R>(J.hv, J.pe, sb, u, s, [&](uint32_t i) { return uk[i]; }, hr, hi, bad);
+          if (bad) hr = hi = (R)NAN;
+        } else {
+          full_row<R>(J.hv, s, uk, u, hr, hi);
+        }
+      }
+      yr[q] = sk * (double)hr;
+      yi[q] = sk * (double)hi;
+    }
+    // <u_i|y> for the window, two vectors per quad_sums
+    for (int i = i0; i <= k; i += 2) {
+      const bool two = i + 1 <= k;
+      double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+#pragma unroll
+      for (int q = 0; q < kFusedNA; ++q) {
+        const uint32_t s = tid + kFusedBlock * q;
+        if (s < D) {
+          const V x0 = ub[(size_t)i * D + s];
+          a0r += (double)x0.x * yr[q] + (double)x0.y * yi[q];
+          a0i += (double)x0.x * yi[q] - (double)x0.y * yr[q];
+          if (two) {
+            const V x1 = ub[(size_t)(i + 1) * D + s];
+            a1r += (double)x1.x * yr[q] + (double)x1.y * yi[q];
+            a1i += (double)x1.x * yi[q] - (double)x1.y * yr[q];
+          }
+        }
+      }
+      const double t = quad_sums(a0r, a0i, a1r, a1i);
+      if (lane < 4u) wred[wv][2 * (i - i0) + lane] = t;
+    }
+    fused_totals(wred, 2 * nw, tot);
+    // alpha_k = s_k Re<u_k|y>, the running ||T||
+    const double alpha = sk * tot[2 * (k - i0)];
+    normT = fmax(normT, fabs(alpha) + off[k]);
+    if (tid == 0) al[k] = alpha;
+    if (last) break;
+    // w = y - sum_i c_i s_i u_i with c_i = s_i <u_i|y>, stored as u_{k+1}
+    double wn = 0.0;
+    V* uo = ub + (size_t)(k + 1) * D;
+#pragma unroll
+    for (int q = 0; q < kFusedNA; ++q) {
+      const uint32_t s = tid + kFusedBlock * q;
+      if (s < D) {
+        double wr = yr[q], wi = yi[q];
+        for (int i = i0; i <= k; ++i) {
+          const double si = sc[i];
+          const double cr = si * si * tot[2 * (i - i0)], ci = si * si * tot[2 * (i - i0) + 1];
+          const V x = ub[(size_t)i * D + s];
+          wr -= cr * x.x - ci * x.y;
+          wi -= cr * x.y + ci * x.x;
+        }
+        V o;
+        o.x = (R)wr;
+        o.y = (R)wi;
+        uo[s] = o;
+        wn += (double)o.x * o.x + (double)o.y * o.y;
+      }
+    }
+    wn = wave_sum(wn);
+    if (lane == 0) wred[wv][0] = wn;
+    fused_totals(wred, 1, tot);
+    // ||w||: the next off-diagonal entry, or a breakdown (an invariant
+    // Krylov space of dimension k + 1)
+    const double bk = sqrt(tot[0]);
+    if (bk <= J.tol * fmax(1.0, normT)) {
+      meff = k + 1;
+      break;
+    }
+    if (tid == 0) {
+      off[k + 1] = bk;
+      sc[k + 1] = 1.0 / bk;
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  // exp(-itT) e_1 on wavefront 0 and the combination coefficients beta0 e_j s_j
+  if (wv == 0) {
+    const int i = (int)lane;
+    double ai = 0.0, lo = 0.0, hi = 0.0;
+    if (i < meff) {
+      ai = al[i];
+      lo = (i > 0) ? off[i] : 0.0;
+      hi = (i + 1 < meff) ? off[i + 1] : 0.0;
+    }
+    double cr, ci;
+    tri_exp_wave(ai, lo, hi, J.t, cr, ci);
+    if (i < meff) dco[i] = cplx_d{beta0 * cr * sc[i], beta0 * ci * sc[i]};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kFusedNA; ++q) {
+    const uint32_t s = tid + kFusedBlock * q;
+    if (s < D) {
+      double orr = 0.0, oi = 0.0;
+      for (int j = 0; j < meff; ++j) {
+        const cplx_d c = dco[j];
+        const V x = ub[(size_t)j * D + s];
+        orr += c.re * x.x - c.im * x.y;
+        oi += c.re * x.y + c.im * x.x;
+      }
+      V o;
+      o.x = (R)orr;
+      o.y = (R)oi;
+      vout[s] = o;
+    }
+  }
+  if (tid == 0 && J.m_eff_out) *J.m_eff_out = meff;
+}
+
+// The one-block form applies when the stored basis fits in LDS and no tile
+// size is forced (KG_TILE_BITS) and KG_NO_FUSED is unset.
+template <typename R>
+bool fused_applies(const KrylovCall& c) {
+  using V = typename VT<R>::T;
+  if (c.geo.D > kFusedMaxD || (size_t)c.m * c.geo.D * sizeof(V) > kFusedLds) return false;
+  const char* tb = getenv("KG_TILE_BITS");
+  const char* nf = getenv("KG_NO_FUSED");
+  return !(tb && *tb) && !(nf && *nf && strcmp(nf, "0") != 0);
+}
+
+template <typename R>
+hipError_t launch_fused_t(const KrylovCall* calls, int n, hipStream_t s) {
+  using V = typename VT<R>::T;
+  // the stored basis may exceed the default 64 KiB of dynamic LDS: raise the
+  // limit of this kernel once per device
+  static std::atomic<uint64_t> raised{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = (dev < 64) ? (1ull << dev) : 0ull;
+  if (!bit || !(raised.load(std::memory_order_acquire) & bit)) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_krylov_fused<R>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds);
+    if (e != hipSuccess) return e;
+    raised.fetch_or(bit, std::memory_order_acq_rel);
+  }
+  FusedBatch fb;
+  memset(&fb, 0, sizeof(fb));
+  for (int j = 0; j < n; ++j) {
+    const KrylovCall& c = calls[j];
+    FusedJob& f = fb.job[j];
+    f.hv = c.hv;
+    if (c.pe) f.pe = *c.pe;
+    f.has_pe = c.pe ? 1 : 0;
+    f.D = c.geo.D;
+    f.m = c.m;
+    f.reorth = c.reorth;
+    f.t = c.t;
+    f.tol = c.tol;
+    f.v_in = c.v_in;
+    f.v_out = c.v_out;
+    f.m_eff_out = c.m_eff_out;
+  }
+  const size_t lds = (size_t)calls[0].m * calls[0].geo.D * sizeof(V);
+  hipLaunchKernelGGL((k_krylov_fused<R>), dim3(n), dim3(kFusedBlock), lds, s, fb);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss, int n, hipStream_t s) {
   using V = typename VT<R>::T;
   const KrylovCall& c0 = calls[0];
+  if (fused_applies<R>(c0)) return launch_fused_t<R>(calls, n, s);
   LzBatch lb;
   CombBatch cb;
   memset(&lb, 0, sizeof(lb));

@@ -43,5 +43,20 @@ def tile_bits(tb):
             os.environ["KG_TILE_BITS"] = old
 
 
+@contextlib.contextmanager
+def tiled_only():
+    """Run Krylov calls through the tiled multi-launch passes even where the
+    one-block form would apply (small vectors)."""
+    old = os.environ.get("KG_NO_FUSED")
+    os.environ["KG_NO_FUSED"] = "1"
+    try:
+        yield
+    finally:
+        if old is None:
+            del os.environ["KG_NO_FUSED"]
+        else:
+            os.environ["KG_NO_FUSED"] = old
+
+
 def xxz_of(c):
     return kg.XXZ(c.L, c.J, c.Delta, c.hc_kind, c.hc_sites)
