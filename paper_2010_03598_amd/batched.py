@@ -151,7 +151,7 @@ class CapturedStep:
 
 
 def autotune(chains: Sequence[BatchChain], n_blocks: Optional[int] = None,
-             caps: Sequence[int] = (1, 2, 4, 8, 16, 32), reps: int = 1):
+             caps: Sequence[int] = (1, 2, 4, 8, 16, 32, 64), reps: int = 1):
     """kg_batched_autotune over team-size caps: returns (Batch planned with the
     fastest cap, {"best_cap", "timings"})."""
     b = Batch(chains, n_blocks=n_blocks, max_team=max(caps), ws_caps=caps)

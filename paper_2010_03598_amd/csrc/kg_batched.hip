@@ -41,10 +41,10 @@ constexpr int kBWB = 4;   // 16 wavefronts
 constexpr int kBThreads = 64 << kBWB;
 constexpr uint32_t kSpinLimit = 1u << 24;
 
+// One arrival word per team member (teams of at most 64): member r writes the
+// number of barriers it has reached to flag[r].
 struct TeamSync {
-  uint32_t count;
-  uint32_t gen;
-  uint32_t pad_[62];
+  uint32_t flag[64];
 };
 
 // Scratch of one chain at kg_chain::off_ws: sync word, two partial buffers,
@@ -69,41 +69,46 @@ struct BCtx {
   int32_t* status;
 };
 
+// Team barrier: every member's device-coherent stores complete, then each
+// member publishes its barrier count in its own arrival word and wavefront 0
+// polls the team's words (one load per lane) until all have reached it.  No
+// read-modify-write and no last-arriver broadcast: an arrival is seen by the
+// others as soon as its store lands.  Bounded spin; a timeout or another
+// team's failure sets or reads the status word and returns false.
 __device__ bool team_barrier(BCtx& c) {
   __shared__ int ok;
   __syncthreads();
   // every wavefront's stores are complete before the block is counted
   complete_stores();
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     int good = 1;
     if (c.team > 1) {
+      const uint32_t lane = threadIdx.x;
       const uint32_t target = c.gen + 1;
-      const uint32_t arrived =
-          __hip_atomic_fetch_add(&c.sync->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
-      if (arrived == c.team) {
-        __hip_atomic_store(&c.sync->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        complete_stores();   // the reset lands before the new generation is seen
-        __hip_atomic_store(&c.sync->gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      } else {
-        uint32_t it = 0;
-        while (__hip_atomic_load(&c.sync->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
-          if (__hip_atomic_load(c.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            good = 0;
-            break;
-          }
-          if (++it > kSpinLimit) {
-            __hip_atomic_store(c.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            good = 0;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(4);
+      if (lane == 0) st_agent_u32(&c.sync->flag[c.member], target);
+      uint32_t it = 0;
+      while (true) {
+        const uint32_t v = (lane < c.team)
+                               ? __hip_atomic_load(&c.sync->flag[lane], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT)
+                               : target;
+        if (__all((int32_t)(v - target) >= 0)) break;
+        if (__hip_atomic_load(c.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+          good = 0;
+          break;
         }
+        if (++it > kSpinLimit) {
+          if (lane == 0) __hip_atomic_store(c.status, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          good = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       c.gen = target;
     }
-    ok = good;
+    if (threadIdx.x == 0) ok = good;
   }
   __syncthreads();
   return ok != 0;
@@ -530,10 +535,9 @@ __global__ void __launch_bounds__(kBThreads)
 
 __global__ void k_batched_init(const kg_chain* chains, int n_chains, char* ws, int32_t* status) {
   const int i = blockIdx.x;
-  if (i < n_chains && threadIdx.x == 0) {
+  if (i < n_chains && threadIdx.x < 64) {
     TeamSync* s = reinterpret_cast<TeamSync*>(ws + chains[i].off_ws);
-    s->count = 0;
-    s->gen = 0;
+    s->flag[threadIdx.x] = 0u;
   }
   if (i == 0 && threadIdx.x == 0) *status = 0;
 }
