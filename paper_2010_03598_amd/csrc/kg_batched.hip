@@ -9,11 +9,12 @@
 // per thread).  Reductions are finished redundantly by every member: each
 // member publishes its block totals, waits at the team barrier and adds the
 // members' totals in member order, so all members hold identical scalars and
-// no member ever waits for a single "last" block.  The barrier is an arrival
-// counter plus a generation word in global memory; its spin is bounded, and a
-// timeout sets the status word, which makes every other waiting member leave as
-// well, so every wavefront of the launch terminates.  Teams of one workgroup
-// synchronise with __syncthreads only.
+// no member ever waits for a single "last" block.  A Lanczos step is one tile
+// pass and one team reduction (team_krylov).  The barrier is one arrival word
+// per member in global memory; its spin is bounded, and a timeout sets the
+// status word, which makes every other waiting member leave as well, so every
+// wavefront of the launch terminates.  Teams of one workgroup synchronise with
+// __syncthreads only.
 //
 // Coherence without device-wide fences: every vector a member writes is stored
 // with device-scope (L2 write-through) stores, and every amplitude a member
@@ -47,8 +48,9 @@ struct TeamSync {
   uint32_t flag[64];
 };
 
-// Scratch of one chain at kg_chain::off_ws: sync word, two partial buffers,
-// the m-1 Krylov basis vectors, the costate vector and y = H v_k.
+// Scratch of one chain at kg_chain::off_ws: arrival words, two partial
+// buffers, the m-1 Krylov basis vectors, the costate vector, y = H u_k and
+// two buffers for w'_k.
 __host__ __device__ inline size_t bws_partials_off() { return 256; }
 __host__ __device__ inline size_t bws_basis_off(int team) {
   const size_t p = 256 + 2 * (size_t)team * kMaxScal * sizeof(cplx_d);
@@ -65,7 +67,8 @@ struct BCtx {
   cplx_d* partials;   // [2][team][kMaxScal]
   float2* basis;
   float2* lam;
-  float2* ybuf;       // y = H v_k of the running step (own tiles only)
+  float2* ybuf;       // y = H u_k of the running step (own tiles only)
+  float2* wbuf;       // w'_k, two vectors by the parity of k (H v partners)
   int32_t* status;
 };
 
@@ -157,7 +160,6 @@ struct KScal {
   cplx_d cdiag[kMaxM];
   cplx_d csub[kMaxM];
   cplx_d gcol[2][kMaxM];
-  cplx_d bmeas[kMaxScal];   // this member's pass B measurements, for the next step's sums
   double beta0;
   double normT;
   int m_eff;
@@ -169,14 +171,24 @@ __device__ __forceinline__ const float2* bslot(const BCtx& c, const float2* in, 
 }
 
 // One Krylov call exp(-i t H) in -> out for the team (out may equal in).
-// Each step k is two passes over the member's tiles, as in the single-chain
-// kernels: pass A forms y = H v_k and only <v_k|y>, ||v_k||^2; the team sums
-// them together with pass B(k-1)'s measurements, and every member runs the
-// scalar update (breakdown test, window dots derived from the measurements,
-// projection coefficients); pass B then reads the window once to form
-// w = s_k y - sum_i c_i v_i and measures <v_j|y> and <v_j|v_k> for the next
-// step's window dots.  A team barrier after pass B makes v_{k+1} visible to
-// the members that read its tiles as H v partners.
+//
+// One tile pass and one team reduction per Lanczos step.  The newest
+// projection coefficient of step k, c_k = s_k^3 <u_k|y_k>, needs a team sum of
+// this step's own H v, so its subtraction is deferred: the pass of step k
+// stores
+//   w'_k = s_k y_k - sum_{i < k in the window} c^(k)_i u_i     (w'_0 = y_0)
+// and the pass of step k+1 materialises the stored vector and its H v as
+//   u_{k+1} = sig_k w'_k - c_k u_k,   y_{k+1} = sig_k H w'_k - c_k y_k,
+// with sig_0 = s_0 = 1/||u_0|| and sig_k = 1 after (H is linear; y_k is the
+// member's own tile, kept from the step before).  The team sums after step k
+// give alpha_k and c_k, ||u_{k+1}||^2 = ||sig w'||^2 - 2 sig Re(conj(c_k)
+// <u_k|w'>) + |c_k|^2 ||u_k||^2 from the pass's measurements, the breakdown
+// test, and the window dots and coefficients of step k+1 (window_dots, from
+// <u_i|y_k> and <u_i|u_k> measured on the stored vectors, as the
+// single-chain passes derive them).  In exact arithmetic u_{k+1} is the
+// vector of Algorithm 2 with every coefficient taken against the same y_k.
+// w'_k is read by other members as H v partners (device-scope stores, two
+// buffers by the parity of k); u_k and y_k only by their own member.
 __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, const float2* in,
                             float2* out, KScal& K, float2* lds, cplx_d* wacc, cplx_d* tot,
                             FinScalars& fs) {
@@ -185,6 +197,7 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
   const int m = ch.m;
   const double u = *c.hv.u_ptr;
+  const uint32_t D = c.geo.D;
   Tile<float, kBRB> T;
   if (threadIdx.x == 0) {
     K.done = 0;
@@ -192,130 +205,27 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
     K.m_eff = m;
   }
   __syncthreads();
-  int i0p = 0;
   for (int k = 0; k < m; ++k) {
     const bool last = (k == m - 1);
     const int i0 = last ? k : (ch.reorth ? 0 : (k > 0 ? k - 1 : 0));
-    const int i0n = (k + 1 == m - 1) ? k + 1 : (ch.reorth ? 0 : k);
     const int nwin = k - i0 + 1;
-    // window dots of step k come from pass B(k-1)'s measurements of nb vectors
-    const int nb = (k > 0 && i0 < k) ? k - i0p : 0;
-    const int ca = 2 * nb, ns = ca + 2;
-    const float2* x = bslot(c, in, k);
-    // ---- pass A(k): y = H x, <x|y> and <x|x>
-    double acc = 0.0;
-    for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
-      __syncthreads();
-      hv_tile<float, kBRB, true>(T, c.hv, c.geo, tile, x, lds, u);
-      const uint32_t s = (tile << kBTB) | lane | (wv << 6);
-      if (!last) c.ybuf[s] = V{T.yr[0], T.yi[0]};   // for pass B of this member
-      const double xr = T.xr[0], xi = T.xi[0], yr = T.yr[0], yi = T.yi[0];
-      acc += quad_sums(xr * yr + xi * yi, xr * yi - xi * yr, xr * xr + xi * xi, 0.0);
-    }
-    __syncthreads();
-    if (lane < 4u) reinterpret_cast<double*>(&wacc[wv * kMaxScal + ca])[lane] = (lane < 3u) ? acc : 0.0;
-    // pass B(k-1)'s block totals join the sums of this step
-    for (int j = threadIdx.x; j < ca; j += blockDim.x) tot[j] = K.bmeas[j];
-    if (k > 0 && threadIdx.x == 0) tot[ns] = K.bmeas[ca];
-    __syncthreads();
-    block_totals(wacc, ns, tot, ca);
-    if (!team_reduce(c, tot, k > 0 ? ns + 1 : ns)) return false;
-    // ---- scalar update of step k on wavefront 0 of every member
-    if (threadIdx.x < 64) {
-      const int l = threadIdx.x;
-      if (k > 0) {
-        // the earlier steps' scalars for the window dots, staged from K
-        fs.alpha[l] = K.alpha[l];
-        fs.offd[l] = K.offd[l];
-        fs.scale[l] = K.scale[l];
-        fs.coef[l] = K.coef[(k - 1) & 1][l];
-        fs.gprev[l] = K.gcol[k & 1][l];
-        fs.cdiag[l] = K.cdiag[l];
-        fs.csub[l] = K.csub[l];
-        if (l == 0) {
-          fs.normT = K.normT;
-          fs.beta0 = K.beta0;
-        }
-      }
-      bool go = true;
-      double sk = 0.0, bk = 0.0;
-      if (k == 0) {
-        const double nn = tot[ca + 1].re;
-        if (!(nn > 0.0)) {
-          // a zero input gives a zero output; a non-finite one a NaN output
-          go = false;
-          if (l == 0) {
-            K.beta0 = (nn == 0.0) ? 0.0 : NAN;
-            K.m_eff = (nn == 0.0) ? 0 : 1;
-            K.alpha[0] = 0.0;
-            K.scale[0] = 1.0;
-            K.done = 1;
-          }
-        } else {
-          sk = 1.0 / sqrt(nn);
-          if (l == 0) {
-            K.beta0 = sqrt(nn);
-            K.scale[0] = sk;
-            K.offd[0] = 0.0;
-          }
-        }
-      } else {
-        // ||w|| of pass B(k-1): the off-diagonal entry of step k, or a breakdown
-        bk = sqrt(tot[ns].re);
-        if (bk <= tol * fmax(1.0, fs.normT)) {
-          go = false;
-          if (l == 0) {
-            K.m_eff = k;
-            K.done = 1;
-          }
-        } else {
-          sk = 1.0 / bk;
-          if (l == 0) {
-            K.offd[k] = bk;
-            K.scale[k] = sk;
-          }
-        }
-      }
-      if (go) {
-        const cplx_d d = (nb > 0) ? window_dots(k, i0, i0p, fs, tot, nb, tot[ns].re, K.gcol[(k - 1) & 1])
-                                  : cplx_d{0.0, 0.0};
-        if (l < nwin) {
-          const int i = i0 + l;
-          const double si = (i == k) ? sk : K.scale[i];
-          const double f = si * sk;
-          const cplx_d tt = (i == k) ? tot[ca] : d;
-          const cplx_d cc{tt.re * f * si, tt.im * f * si};
-          K.coef[k & 1][l] = cc;
-          if (i == k) K.cdiag[k] = cc;
-          if (i == k - 1) K.csub[k] = cc;
-        }
-        const double alpha = tot[ca].re * sk * sk;
-        if (l == 0) {
-          K.alpha[k] = alpha;
-          K.normT = fmax(k == 0 ? 0.0 : fs.normT, fabs(alpha) + (k == 0 ? 0.0 : bk));
-          if (last) {
-            K.m_eff = m;
-            K.done = 1;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    i0p = i0;
-    if (K.done) break;
-    // ---- pass B(k): w = s_k y - sum_i c_i v_i -> stored v_{k+1}; ||w||^2 and,
-    // when step k+1 has window dots, <v_j|y> (columns [0, nbo)) and <v_j|v_k>
-    // (columns [nbo, 2nbo)) for the window vectors j
-    const int nbo = (i0n <= k) ? nwin : 0;
-    const double sk = K.scale[k];
+    // measurement columns: <u_i|y_k> at i - i0, <u_i|u_k> at nwin + i - i0
+    // (i in [i0, k]), ||w'||^2 at 2 nwin, <u_k|w'> at 2 nwin + 1
+    const int ncol = 2 * nwin + 2;
+    const float2* hsrc = (k == 0) ? in : c.wbuf + (size_t)((k - 1) & 1) * D;
+    const double sig = (k == 1) ? K.scale[0] : 1.0;
+    const cplx_d cl = (k >= 1) ? K.cdiag[k - 1] : cplx_d{0.0, 0.0};
+    const double sk = (k >= 1) ? K.scale[k] : 1.0;
     const cplx_d* cf = K.coef[k & 1];
-    float2* vout = c.basis + (size_t)k * c.geo.D;
+    float2* uk = (k >= 1) ? c.basis + (size_t)(k - 1) * D : nullptr;
+    const float2* ul = (k >= 1) ? bslot(c, in, k - 1) : nullptr;
+    float2* wk = c.wbuf + (size_t)(k & 1) * D;
     cplx_d* wrow = wacc + wv * kMaxScal;
-    for (int j = (int)lane; j < 2 * nbo; j += 64) wrow[j] = cplx_d{0.0, 0.0};
-    double bnn = 0.0;
-    const auto add_quad = [&](int w, double tq) {
+    for (int j = (int)lane; j < ncol; j += 64) wrow[j] = cplx_d{0.0, 0.0};
+    const auto add_quad = [&](int col0, int col1, double tq) {
+      // lanes 0, 1: column col0 (re, im); lanes 2, 3: column col1
       if (lane < 4u) {
-        cplx_d& d = wrow[(lane < 2u ? 0 : nbo) + w];
+        cplx_d& d = wrow[lane < 2u ? col0 : col1];
         if (lane & 1u) {
           d.im += tq;
         } else {
@@ -324,17 +234,28 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
       }
     };
     for (uint32_t tile = c.member; tile < c.geo.ntiles; tile += c.team) {
+      __syncthreads();
+      hv_tile<float, kBRB, true>(T, c.hv, c.geo, tile, hsrc, lds, u);
       const uint32_t s = (tile << kBTB) | lane | (wv << 6);
-      const V yv = c.ybuf[s];
-      const V xv = x[s];
-      const double yr = yv.x, yi = yv.y, xr = xv.x, xi = xv.y;
-      double zr, zi;
-      {
-        const cplx_d cc = cf[k - i0];
-        zr = sk * yr - (cc.re * xr - cc.im * xi);
-        zi = sk * yi - (cc.re * xi + cc.im * xr);
+      // u_k and y_k, rounded as stored
+      V uo, yo;
+      if (k == 0) {
+        uo = V{T.xr[0], T.xi[0]};
+        yo = V{T.yr[0], T.yi[0]};
+      } else {
+        const V up = ul[s], yp = c.ybuf[s];
+        uo.x = (float)(sig * (double)T.xr[0] - (cl.re * up.x - cl.im * up.y));
+        uo.y = (float)(sig * (double)T.xi[0] - (cl.re * up.y + cl.im * up.x));
+        yo.x = (float)(sig * (double)T.yr[0] - (cl.re * yp.x - cl.im * yp.y));
+        yo.y = (float)(sig * (double)T.yi[0] - (cl.re * yp.y + cl.im * yp.x));
+        uk[s] = uo;
       }
-      if (nbo) add_quad(k - i0, quad_sums(xr * yr + xi * yi, xr * yi - xi * yr, xr * xr + xi * xi, 0.0));
+      if (!last) c.ybuf[s] = yo;
+      const double xr = uo.x, xi = uo.y, yr = yo.x, yi = yo.y;
+      // <u_k|y_k>, ||u_k||^2
+      add_quad(nwin - 1, 2 * nwin - 1, quad_sums(xr * yr + xi * yi, xr * yi - xi * yr, xr * xr + xi * xi, 0.0));
+      double zr = sk * yr, zi = sk * yi;
+      // the window before u_k, eight vectors per round trip
       for (int i = i0; i < k; i += 8) {
         V q[8];
 #pragma unroll
@@ -343,27 +264,121 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           if (i + j < k) {
-            const cplx_d cc = cf[i + j - i0];
             const double vr = q[j].x, vi = q[j].y;
+            const cplx_d cc = cf[i + j - i0];
             zr -= cc.re * vr - cc.im * vi;
             zi -= cc.re * vi + cc.im * vr;
-            if (nbo)
-              add_quad(i + j - i0, quad_sums(vr * yr + vi * yi, vr * yi - vi * yr,
-                                             vr * xr + vi * xi, vr * xi - vi * xr));
+            add_quad(i + j - i0, nwin + i + j - i0,
+                     quad_sums(vr * yr + vi * yi, vr * yi - vi * yr, vr * xr + vi * xi, vr * xi - vi * xr));
           }
         }
       }
-      V o;
-      o.x = (float)zr;
-      o.y = (float)zi;
-      st_coh(&vout[s], o);      // read by other members as H v partners
-      bnn += wave_sum((double)o.x * (double)o.x + (double)o.y * (double)o.y);
+      if (!last) {
+        V o;
+        o.x = (float)zr;
+        o.y = (float)zi;
+        st_coh(&wk[s], o);      // read by other members as H v partners
+        const double orr = o.x, oi = o.y;
+        add_quad(2 * nwin, 2 * nwin + 1,
+                 quad_sums(orr * orr + oi * oi, 0.0, xr * orr + xi * oi, xr * oi - xi * orr));
+      }
     }
-    if (lane == 0) wrow[2 * nbo] = cplx_d{bnn, 0.0};
     __syncthreads();
-    block_totals(wacc, 2 * nbo + 1, K.bmeas);
-    // v_{k+1} complete in every member before any member reads its partners
-    if (!team_barrier(c)) return false;
+    block_totals(wacc, ncol, tot);
+    if (!team_reduce(c, tot, ncol)) return false;
+    // ---- scalars after step k (wavefront 0 of every member, the same values)
+    if (threadIdx.x < 64) {
+      const int l = threadIdx.x;
+      fs.alpha[l] = K.alpha[l];
+      fs.offd[l] = K.offd[l];
+      fs.scale[l] = K.scale[l];
+      fs.coef[l] = K.coef[k & 1][l];
+      fs.gprev[l] = K.gcol[(k + 1) & 1][l];
+      fs.cdiag[l] = K.cdiag[l];
+      fs.csub[l] = K.csub[l];
+      const cplx_d tkk = tot[nwin - 1];
+      const double ukk = tot[2 * nwin - 1].re;
+      bool go = true;
+      double s = sk;
+      if (k == 0) {
+        if (!(ukk > 0.0)) {
+          // a zero input gives a zero output; a non-finite one a NaN output
+          go = false;
+          if (l == 0) {
+            K.beta0 = (ukk == 0.0) ? 0.0 : NAN;
+            K.m_eff = (ukk == 0.0) ? 0 : 1;
+            K.alpha[0] = 0.0;
+            K.scale[0] = 1.0;
+            K.done = 1;
+          }
+        } else {
+          s = 1.0 / sqrt(ukk);
+          if (l == 0) {
+            K.beta0 = sqrt(ukk);
+            K.scale[0] = s;
+            K.offd[0] = 0.0;
+          }
+          fs.scale[0] = s;
+        }
+      }
+      if (go) {
+        // alpha_k and c^(k)_k
+        const double alpha = tkk.re * s * s;
+        const cplx_d ckk{tkk.re * s * s * s, tkk.im * s * s * s};
+        const double normT = fmax(k == 0 ? 0.0 : K.normT, fabs(alpha) + (k == 0 ? 0.0 : K.offd[k]));
+        if (l == k - i0) fs.coef[l] = ckk;
+        if (l == k) fs.cdiag[l] = ckk;
+        if (l == 0) {
+          K.alpha[k] = alpha;
+          K.coef[k & 1][k - i0] = ckk;
+          K.cdiag[k] = ckk;
+          K.normT = normT;
+        }
+        if (last) {
+          if (l == 0) {
+            K.m_eff = m;
+            K.done = 1;
+          }
+        } else {
+          // ||u_{k+1}||^2 of the deferred subtraction, or a breakdown (an
+          // invariant Krylov space of dimension k + 1)
+          const double sg = (k == 0) ? s : 1.0;
+          const cplx_d pw = tot[2 * nwin + 1];
+          double b2 = sg * sg * tot[2 * nwin].re - 2.0 * sg * (ckk.re * pw.re + ckk.im * pw.im) +
+                      (ckk.re * ckk.re + ckk.im * ckk.im) * ukk;
+          b2 = fmax(b2, 0.0);
+          const double bk = sqrt(b2);
+          if (bk <= tol * fmax(1.0, normT)) {
+            if (l == 0) {
+              K.m_eff = k + 1;
+              K.done = 1;
+            }
+          } else {
+            const double sn = 1.0 / bk;
+            if (l == 0) {
+              K.offd[k + 1] = bk;
+              K.scale[k + 1] = sn;
+            }
+            // window dots and coefficients of step k + 1 (all but the newest)
+            const int kn = k + 1;
+            const int i0n = (kn == m - 1) ? kn : (ch.reorth ? 0 : kn - 1);
+            const int nwn = kn - i0n + 1;
+            if (nwn > 1) {
+              const cplx_d d = window_dots(kn, i0n, i0, fs, tot, nwin, b2, K.gcol[k & 1]);
+              if (l < nwn - 1) {
+                const int i = i0n + l;
+                const double si = fs.scale[i];
+                const cplx_d cc{d.re * si * si * sn, d.im * si * si * sn};
+                K.coef[kn & 1][l] = cc;
+                if (i == k) K.csub[kn] = cc;
+              }
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (K.done) break;
   }
   // ---- exp(-itT) e_1 on wavefront 0 and the combination coefficients
   const int me = K.m_eff;
@@ -441,8 +456,9 @@ __global__ void __launch_bounds__(kBThreads)
               const float2* psi0_all, const float2* target_all, float2* states_all, double* F_all,
               double* beta_all, double* grad_all, char* ws, int32_t* status) {
   extern __shared__ unsigned char smem_raw[];
+  // the H v tile, then the per-wavefront accumulator rows (used together)
   float2* lds = reinterpret_cast<float2*>(smem_raw);
-  cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw);
+  cplx_d* wacc = reinterpret_cast<cplx_d*>(smem_raw + ((size_t)1 << kBTB) * sizeof(float2));
   __shared__ cplx_d tot[kMaxScal];
   __shared__ KScal K;
   __shared__ FinScalars fs;
@@ -468,6 +484,7 @@ __global__ void __launch_bounds__(kBThreads)
   const uint32_t D = 1u << L;
   c.lam = c.basis + (size_t)(ch.m > 1 ? ch.m - 1 : 0) * D;
   c.ybuf = c.lam + D;
+  c.wbuf = c.ybuf + D;
   c.status = status;
   c.geo.L = L;
   c.geo.TB = kBTB;
@@ -546,7 +563,8 @@ __global__ void k_batched_init(const kg_chain* chains, int n_chains, char* ws, i
 
 size_t batched_chain_ws_bytes(int L, int m, int team) {
   const size_t vb = ((size_t)1 << L) * sizeof(float2);
-  return bws_basis_off(team) + vb * (size_t)(m > 1 ? m - 1 : 0) + 2 * vb;
+  // basis, costate, y, and the two w' buffers
+  return bws_basis_off(team) + vb * (size_t)(m > 1 ? m - 1 : 0) + 4 * vb;
 }
 
 hipError_t launch_batched(const kg_chain* chains_dev, int n_chains, int n_blocks, const double* u_all,
@@ -559,7 +577,7 @@ hipError_t launch_batched(const kg_chain* chains_dev, int n_chains, int n_blocks
   if (e != hipSuccess) return e;
   const size_t tile = ((size_t)1 << kBTB) * sizeof(float2);
   const size_t red = ((size_t)kBThreads / 64) * kMaxScal * sizeof(cplx_d);
-  hipLaunchKernelGGL(k_batched, dim3(n_blocks), dim3(kBThreads), tile > red ? tile : red, s,
+  hipLaunchKernelGGL(k_batched, dim3(n_blocks), dim3(kBThreads), tile + red, s,
                      chains_dev, n_chains, u_all, reinterpret_cast<const float2*>(psi0_all),
                      reinterpret_cast<const float2*>(target_all), reinterpret_cast<float2*>(states_all),
                      F_all, beta_all, grad_all, static_cast<char*>(ws), status);
