@@ -434,18 +434,23 @@ def fig2b(kg, torch, workloads, sizes, max_iter=300):
 
 def batched_algorithmic_bytes(chains, ms):
     """Bytes the batched launch must move (complex64 vectors, 8 B per amplitude):
-    per chain, 2N-1 Krylov calls (store-all: no recomputation), each with pass A
-    reading v_k and writing y (no y in the last step), pass B reading y and the
-    window and writing the next vector, and the combination reading m vectors
-    and writing one; N brackets and the overlap read two vectors."""
+    per chain, 2N-1 Krylov calls (store-all: no recomputation), each with one
+    tile pass per Lanczos step -- step 0 reads the input and writes y_0 and w'_0;
+    a later step reads w'_{k-1} (its H v), u_{k-1}, y_{k-1} and the window
+    before u_k and writes u_k, y_k and w'_k (the last step only u_k) -- and the
+    combination reading m vectors and writing one; N brackets and the overlap
+    read two vectors."""
     total = 0
     for c, m in zip(chains, ms):
         V = 8 << c.h.L
         per_call = 0
         for k in range(m):
             last = k == m - 1
-            nw = 1 if last else (k + 1 if c.reorth else min(k + 1, 2))
-            per_call += (1 + (0 if last else 1)) + (0 if last else nw + 2)
+            if k == 0:
+                per_call += 1 + (0 if last else 2)
+            else:
+                before = 0 if last else (k if c.reorth else 1)
+                per_call += 3 + before + (1 if last else 3)
         per_call += m + 1
         total += V * ((2 * c.N - 1) * per_call + 2 * c.N + 2)
     return total
