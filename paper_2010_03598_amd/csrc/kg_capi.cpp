@@ -565,6 +565,7 @@ Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap, bool standal
   g.WB = tb - 6 - g.RB;
   g.small = (L < g.TB) ? 1 : 0;
   g.ntiles = g.small ? 1u : (1u << (L - g.TB));
+  if (grid_cap == kLzGrid && g.ntiles >= kLzManyTiles) grid_cap = kLzGridLarge;
   g.grid = (int)(g.ntiles < (uint32_t)grid_cap ? g.ntiles : (uint32_t)grid_cap);
   return g;
 }

@@ -15,8 +15,12 @@ constexpr int kMaxScal = 2 * kMaxM + 3;
 constexpr int kMaxGrid = 2048;     // largest grid of the reducing kernels
 constexpr int kPartialRows = kMaxGrid + kMaxGrid / 64;  // block rows + group rows
 // largest grid of the Lanczos passes: every block of pass B reads the pass A
-// partials of all of them (32 bytes a row)
+// partials of all of them (32 bytes a row), so the grid stays at 512 blocks
+// unless the vector has at least kLzManyTiles tiles, where kLzGridLarge blocks
+// stream it faster (Krylov calls at L=23 and 24, complex64: 3 and 4.5 %)
 constexpr int kLzGrid = 512;
+constexpr int kLzGridLarge = 2048;
+constexpr uint32_t kLzManyTiles = 4096;
 
 struct cplx_d {                    // complex FP64 with a fixed layout
   double re, im;
