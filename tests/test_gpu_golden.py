@@ -1,6 +1,7 @@
 """GPU results at the workloads' real sizes against the oracle's stored values
 (tests/golden/*.json, written by tests/golden/make_golden.py from the oracle
-alone): the L=16 gradient-ascent run, and short-N instances of the L=24 chain."""
+alone): the L=16 gradient-ascent run, the L=20 adjoint workload with all 400
+slices, and short-N instances of the L=24 chain."""
 
 import json
 import os
@@ -95,3 +96,12 @@ def gradient_vs_golden(name, c, dtype, tol, ckpt_every, reorth=True):
 def test_adjoint_plain_lanczos(dtype, tol):
     """Plain Lanczos (three-term window) policy to policy: L=20, N=8, m=20."""
     gradient_vs_golden("adjoint_short_plain", workloads.adjoint(N=8), dtype, tol, 4, reorth=False)
+
+
+@pytest.mark.parametrize("dtype,tol", [(C128, 1e-10), (C64, 1e-4)])
+def test_adjoint_workload_all_slices(dtype, tol):
+    """The adjoint workload at its real size (L=20, N=400, m=20, checkpoints
+    every 20, so 18 segments are recomputed beside the costate sweep): F, beta
+    and every slice's gradient against the oracle's full run."""
+    gradient_vs_golden("adjoint_full", workloads.adjoint(), dtype, tol,
+                       workloads.ADJOINT_CKPT_EVERY)
