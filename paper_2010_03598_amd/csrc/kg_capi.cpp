@@ -542,15 +542,15 @@ Geo make_geo(int L, int prec, int tile_bits_override, int grid_cap, bool standal
   // complex64 tiles of 2^13 (eight amplitudes per thread, 1024 threads) only
   // for the standalone H v: the Lanczos passes keep at most 2^12
   const int tb_max = (standalone && prec == KG_C64) ? 13 : 12;
-  // default tile, from Krylov-call timings at L = 16..26: 2^9..2^11
-  // amplitudes up to L = 18 (complex64) or L = 19 (complex128), the largest
-  // tile beyond; complex64 vectors of 2^23 amplitudes and more go back to
-  // 2^11 (more tiles per block, 1-3.5 % faster per Krylov call at L = 23..26)
+  // default tile, from timed gradients (m = 20, checkpointed): complex64
+  // 2^9 amplitudes up to L = 17, 2^10 at L = 18 and 2^11 from L = 19 (2^11
+  // against 2^12: 9, 2, 7 and 2 % faster at L = 19..22, 3-4.5 % per Krylov
+  // call at L = 23, 24); complex128 2^9..2^11 up to L = 19 and 2^12 beyond
   int tb;
   if (prec == KG_C128) {
     tb = (L >= 20) ? 12 : std::min(std::max(L - 8, 9), 12);
   } else {
-    tb = (L >= 23) ? 11 : (L >= 19) ? 12 : std::min(std::max(L - 7, 9), 11);
+    tb = (L >= 19) ? 11 : (L == 18 ? 10 : 9);
   }
   if (tile_bits_override >= 6) tb = tile_bits_override;
   if (tb > tb_max) tb = tb_max;
