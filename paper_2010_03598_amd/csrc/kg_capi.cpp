@@ -477,7 +477,8 @@ struct Profiler {
   long launches = 0;
   std::vector<hipEvent_t> ev;
   int used = 0;
-  int pending = -1;
+  int armed = -1;      // first of the armed event pair, or -1
+  bool taken = false;  // a launch took the armed pair
   struct Rec {
     int cls;
     double bytes;
@@ -503,18 +504,30 @@ Profiler* profiler_for_launch() {
 }
 
 void profiler_start(Profiler* p, hipStream_t s) {
-  p->pending = -1;
+  (void)s;
+  p->armed = -1;
+  p->taken = false;
   if (p->used + 2 > (int)p->ev.size()) return;
-  if (hipEventRecord(p->ev[p->used], s) != hipSuccess) return;
-  p->pending = p->used++;
+  p->armed = p->used;
+}
+
+bool profiler_take(hipEvent_t* e0, hipEvent_t* e1) {
+  Profiler* p = g_prof;
+  if (!p || p->armed < 0 || p->taken) return false;
+  *e0 = p->ev[p->armed];
+  *e1 = p->ev[p->armed + 1];
+  p->taken = true;
+  return true;
 }
 
 void profiler_stop(Profiler* p, hipStream_t s, int cls, double bytes) {
-  if (p->pending < 0) return;
-  if (hipEventRecord(p->ev[p->used], s) != hipSuccess) return;
-  p->recs.push_back(Profiler::Rec{cls, bytes, p->pending, p->used});
-  p->used++;
-  p->pending = -1;
+  (void)s;
+  if (p->armed >= 0 && p->taken) {
+    p->recs.push_back(Profiler::Rec{cls, bytes, p->armed, p->armed + 1});
+    p->used += 2;
+  }
+  p->armed = -1;
+  p->taken = false;
 }
 
 size_t vec_bytes(int L, int prec) { return ((size_t)1 << L) * (prec == KG_C128 ? 16 : 8); }

@@ -106,8 +106,13 @@ struct Profiler;
 // Non-null while profiling is active and the current Krylov call is sampled.
 Profiler* profiler_for_call();
 Profiler* profiler_for_launch();
+// profiler_start arms a pair of events for the next sampled launch, which
+// takes them with profiler_take and passes them to the dispatch itself
+// (hipExtLaunchKernel: the kernel's own start and end, as a kernel trace
+// records them); profiler_stop files the record if a launch took them.
 void profiler_start(Profiler* p, hipStream_t s);
 void profiler_stop(Profiler* p, hipStream_t s, int cls, double bytes);
+bool profiler_take(hipEvent_t* e0, hipEvent_t* e1);
 
 // ---- launchers (kg_kernels.hip); all enqueue on `s` and return hipSuccess or the launch error
 hipError_t launch_hv(int prec, const HvArgs& a, const Geo& g, const void* v, void* w, hipStream_t s);

@@ -46,6 +46,7 @@
 // XCD b%8, and the tiles of one XCD form one contiguous range, so partner tiles
 // of the lower hopping bonds are read from the same L2.
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -59,6 +60,20 @@
 #include "kg_internal.h"
 
 namespace kg {
+
+// A kernel launch that takes the profiler's armed event pair when one is
+// armed (the dispatch records the kernel's own start and end), and a plain
+// launch otherwise.
+template <typename... Args, typename F = void (*)(Args...)>
+inline void kg_launch(F kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+  hipEvent_t e0, e1;
+  if (profiler_take(&e0, &e1)) {
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)lds, s, e0, e1, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+  }
+}
+
 namespace {
 
 // ---------------------------------------------------------------------- xxz_apply
@@ -1166,12 +1181,12 @@ hipError_t launch_hv_t(const HvArgs& a, const Geo& g, const void* v, void* w, hi
                      (((uintptr_t)v | (uintptr_t)w) % 16) == 0;
   if constexpr (sizeof(R) == 4 && RB >= 2) {
     if (pairs) {
-      hipLaunchKernelGGL((k_hv<R, RB, true>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, a,
+      kg_launch((k_hv<R, RB, true>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, a,
                          g, reinterpret_cast<const V*>(v), reinterpret_cast<V*>(w));
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_hv<R, RB>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, a, g,
+  kg_launch((k_hv<R, RB>), dim3(g.grid), dim3(64 << g.WB), lds_bytes<R>(g), s, a, g,
                      reinterpret_cast<const V*>(v), reinterpret_cast<V*>(w));
   return hipGetLastError();
 }
@@ -1185,7 +1200,7 @@ hipError_t launch_hv_pe_t(const HvArgs& a, const PeArgs& p, const void* v, void*
   if (blocks > 8192u) blocks = 8192u;
   if (blocks < 1u) blocks = 1u;
   if (blocks >= 64u) blocks = (blocks + 7u) & ~7u;
-  hipLaunchKernelGGL((k_hv_pe<R>), dim3(blocks), dim3(256), 0, s, a, p, reinterpret_cast<const V*>(v),
+  kg_launch((k_hv_pe<R>), dim3(blocks), dim3(256), 0, s, a, p, reinterpret_cast<const V*>(v),
                      reinterpret_cast<V*>(w));
   return hipGetLastError();
 }
@@ -1212,11 +1227,11 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
     }
     if constexpr (sizeof(R) == 4 && RB >= 2) {
       if (pairs) {
-        hipLaunchKernelGGL((k_pass_a<R, RB, true>), grid, block, lds_bytes<R>(g), s, lb);
+        kg_launch((k_pass_a<R, RB, true>), grid, block, lds_bytes<R>(g), s, lb);
         return hipGetLastError();
       }
     }
-    hipLaunchKernelGGL((k_pass_a<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
+    kg_launch((k_pass_a<R, RB>), grid, block, lds_bytes<R>(g), s, lb);
   } else {
     const size_t red = ((size_t)1 << g.WB) * kMaxScal * sizeof(cplx_d);
     // 16-byte pairs need whole tiles and 16-byte aligned vectors (the boundary
@@ -1228,12 +1243,12 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
       if (((uintptr_t)q.slot0 | (uintptr_t)q.basis | (uintptr_t)q.yk) % 16) pairs = false;
     }
     if (g.small) {
-      hipLaunchKernelGGL((k_pass_b<R, RB, kBMasked>), grid, block, red, s, lb);
+      kg_launch((k_pass_b<R, RB, kBMasked>), grid, block, red, s, lb);
     } else if (pairs) {
-      hipLaunchKernelGGL((k_pass_b<R, RB, (sizeof(R) == 4 && RB >= 1) ? kBPairs : kBSlots>), grid, block,
+      kg_launch((k_pass_b<R, RB, (sizeof(R) == 4 && RB >= 1) ? kBPairs : kBSlots>), grid, block,
                          red, s, lb);
     } else {
-      hipLaunchKernelGGL((k_pass_b<R, RB, kBSlots>), grid, block, red, s, lb);
+      kg_launch((k_pass_b<R, RB, kBSlots>), grid, block, red, s, lb);
     }
   }
   return hipGetLastError();
@@ -1607,23 +1622,23 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
     const int nwin = k - i0 + 1;
     if (c0.pe) {
       // reduced basis: y = H v_k by the gather kernel, then pass A on the given y
-      if (prof) profiler_start(prof, s);
       for (int j = 0; j < n; ++j) {
         const char* xk = (k == 0) ? static_cast<const char*>(calls[j].v_in)
                                   : static_cast<const char*>(wss[j]->basis) +
                                         (size_t)(k - 1) * c0.geo.D * sizeof(V);
         void* yk = wss[j]->yk;
+        if (prof) profiler_start(prof, s);
         if ((e = launch_hv_pe_t<R>(lb.job[j].hv, *calls[j].pe, xk, yk, s)) != hipSuccess)
           return e;
+        // x read, y written, and the orbit label and rank of every output read
+        if (prof) profiler_stop(prof, s, kProfHv, (vb / n) * 2.0 + (double)c0.geo.D * 8.0);
       }
-      // x read, y written, and the orbit label and rank of every output read
-      if (prof) profiler_stop(prof, s, kProfHv, vb * 2.0 + (double)c0.geo.D * 8.0 * n);
     }
     if (prof) profiler_start(prof, s);
     if (c0.pe) {
       const Geo& g = c0.geo;
       const size_t red = ((size_t)1 << g.WB) * kMaxScal * sizeof(cplx_d);
-      hipLaunchKernelGGL((k_pass_a_y<R>), dim3(g.grid * n), dim3(64 << g.WB), red, s, lb);
+      kg_launch((k_pass_a_y<R>), dim3(g.grid * n), dim3(64 << g.WB), red, s, lb);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     } else if ((e = launch_pass_r<R>(true, lb, n, s)) != hipSuccess) {
       return e;
@@ -1646,7 +1661,7 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
   cb.D = D;
   cb.grid = (uint32_t)stream_grid(D);
   if (prof) profiler_start(prof, s);
-  hipLaunchKernelGGL((k_combine<R>), dim3(cb.grid * n), dim3(kStreamBlock), 0, s, cb);
+  kg_launch((k_combine<R>), dim3(cb.grid * n), dim3(kStreamBlock), 0, s, cb);
   e = hipGetLastError();
   // m basis vectors read (fewer after a breakdown), v_out written
   if (prof) profiler_stop(prof, s, kProfCombine, (c0.m + 1) * vb);
@@ -1703,11 +1718,11 @@ hipError_t launch_overlap(int prec, uint32_t D, const void* f, const void* psi, 
                           double* F_dev, double* beta_dev, hipStream_t s) {
   const int grid = reduce_grid(D, prec);
   if (prec == 0) {
-    hipLaunchKernelGGL(k_overlap<double>, dim3(grid), dim3(kStreamBlock), 0, s, D,
+    kg_launch(k_overlap<double>, dim3(grid), dim3(kStreamBlock), 0, s, D,
                        reinterpret_cast<const double2*>(f), reinterpret_cast<const double2*>(psi),
                        ws.st, ws.partials, F_dev, beta_dev);
   } else {
-    hipLaunchKernelGGL(k_overlap<float>, dim3(grid), dim3(kStreamBlock), 0, s, D,
+    kg_launch(k_overlap<float>, dim3(grid), dim3(kStreamBlock), 0, s, D,
                        reinterpret_cast<const float2*>(f), reinterpret_cast<const float2*>(psi),
                        ws.st, ws.partials, F_dev, beta_dev);
   }
@@ -1721,11 +1736,11 @@ hipError_t launch_bracket(int prec, const HvArgs& a, uint32_t D, const void* lam
   const int grid = reduce_grid(D, prec);
   const int acc = accumulate ? 1 : 0;
   if (prec == 0) {
-    hipLaunchKernelGGL(k_bracket<double>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
+    kg_launch(k_bracket<double>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const double2*>(lam), reinterpret_cast<const double2*>(psi),
                        dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc, pe_reps);
   } else {
-    hipLaunchKernelGGL(k_bracket<float>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
+    kg_launch(k_bracket<float>, dim3(grid), dim3(kStreamBlock), 0, s, a, D,
                        reinterpret_cast<const float2*>(lam), reinterpret_cast<const float2*>(psi),
                        dt, coef_im, beta_dev, ws.st, ws.partials, grad_slot, acc, pe_reps);
   }
