@@ -105,3 +105,12 @@ def test_adjoint_workload_all_slices(dtype, tol):
     and every slice's gradient against the oracle's full run."""
     gradient_vs_golden("adjoint_full", workloads.adjoint(), dtype, tol,
                        workloads.ADJOINT_CKPT_EVERY)
+
+
+@pytest.mark.parametrize("dtype,tol", [(C128, 1e-10), (C64, 1e-4)])
+def test_large_chain_checkpointed(dtype, tol):
+    """L=24 (the large form's vector size and Krylov dimension 24), N=6 slices
+    with a checkpoint every 2: three segments, so the first is recomputed from
+    psi_0 beside the costate propagation of the second, at the large form's
+    tiles and grid."""
+    gradient_vs_golden("large_ckpt", workloads.large(N=6), dtype, tol, 2)
