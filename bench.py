@@ -373,7 +373,12 @@ def time_pe(kg, torch, workloads, steps=2, reps=20):
         e1_.record()
         e1_.synchronize()
         best = min(best, e0.elapsed_time(e1_) * 1e-3 / reps)
-    hv_bytes = B.dim * (2 * x.element_size() + 8)   # x read, y written, labels and ranks read
+    # x read, y written, the labels read, and the neighbour slots the slices
+    # use (the labels' ranks instead when the basis has no neighbour table)
+    if "slot_counts" in tab:
+        hv_bytes = B.dim * (2 * x.element_size() + 4) + 256 * int(tab["slot_counts"].sum())
+    else:
+        hv_bytes = B.dim * (2 * x.element_size() + 8)
     kern = {c: {"launches_timed": v["launches"], "avg_us": v["ms"] / v["launches"] * 1e3,
                 "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
             for c, v in prof.items() if v["launches"]}
@@ -391,6 +396,7 @@ def time_pe(kg, torch, workloads, steps=2, reps=20):
             "hv_pe": {"us_per_launch": best * 1e6, "algorithmic_bytes": hv_bytes,
                       "algorithmic_GBps": hv_bytes / best / 1e9,
                       "frac_of_peak": hv_bytes / best / 1e9 / HBM_PEAK_GBS,
+                      "gather": "neighbour table" if "slot_counts" in tab else "ranks formed",
                       "timing": "HIP graph of the launches, best of 3 replays"}}
 
 

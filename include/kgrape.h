@@ -332,7 +332,20 @@ size_t kg_pe_tables_bytes(int32_t L, int32_t K);
  *   byte 4608 + R:     the combinatorial rank of each label (uint32, dim);
  *   byte 4608 + 2 R:   the orbit index (int32) of every sector pattern s at
  *                      its combinatorial rank sum_i C(z_i, i) over the zero-bit
- *                      positions z_1 < z_2 < ... of s (C(L, K) entries).
+ *                      positions z_1 < z_2 < ... of s (C(L, K) entries);
+ * then, for bases with S = ceil(dim / 64) slices of 64 rows and
+ * S * 64 * (L - 1) <= 2^30 (every K up to L = 28), a neighbour table, each section
+ * at the next 256-byte boundary:
+ *   slot counts:       uint32 per slice, the largest number of antiparallel
+ *                      bonds among its labels;
+ *   neighbours:        uint32, L - 1 slots per row: slot j of row 64 s + l at
+ *                      [(s (L - 1) + j) 64 + l] holds a | c << 30, a the orbit
+ *                      reached through the label's j-th antiparallel bond
+ *                      (ascending), c = 1, 2, 3 for sqrt(n_b / n_a) = 1,
+ *                      sqrt 2, 1/sqrt 2; unused slots hold the row's own index
+ *                      with c = 0 (rows past dim: 0).
+ * The reduced H v gathers through the neighbour table when it is there and
+ * forms the ranks itself otherwise, with the same sums either way.
  * A caller may copy this image to device memory itself and fill a kg_pe with
  * it.  Errors: KG_EINVAL, KG_EWORKSPACE. */
 kg_status kg_pe_tables_host(int32_t L, int32_t K, void* tables_host, size_t tables_bytes);

@@ -14,6 +14,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -1324,18 +1326,41 @@ int64_t pe_dim(int L, int K) {
 
 // Table layout in the caller's buffer: binomials (uint32, kPeBinom^2), orbit
 // representatives (uint32, dim), their ranks (uint32, dim), index by
-// combinatorial rank (int32, C(L,K)), each at a 256-byte boundary.
+// combinatorial rank (int32, C(L,K)), each at a 256-byte boundary; then, for
+// bases of at most kPeNbrMaxEntries neighbour slots, the slot count of each
+// slice of 64 rows (uint32) and the neighbour slots (uint32, L - 1 per row).
 struct PeLayout {
-  size_t off_reps, off_ranks, off_index, total;
+  size_t off_reps, off_ranks, off_index, off_scnt, off_nbr, total;
+  uint64_t nslices;
+  int nbr_slots;           // 0: no neighbour table
 };
 
 PeLayout pe_layout(int L, int K) {
   PeLayout o;
+  const uint64_t dim = (uint64_t)pe_dim(L, K);
   o.off_reps = align_up(sizeof(uint32_t) * kPeBinom * kPeBinom, 256);
-  o.off_ranks = o.off_reps + align_up(sizeof(uint32_t) * (size_t)pe_dim(L, K), 256);
-  o.off_index = o.off_ranks + align_up(sizeof(uint32_t) * (size_t)pe_dim(L, K), 256);
-  o.total = o.off_index + align_up(sizeof(int32_t) * (size_t)pascal().c[L][K], 256);
+  o.off_ranks = o.off_reps + align_up(sizeof(uint32_t) * (size_t)dim, 256);
+  o.off_index = o.off_ranks + align_up(sizeof(uint32_t) * (size_t)dim, 256);
+  o.off_scnt = o.off_index + align_up(sizeof(int32_t) * (size_t)pascal().c[L][K], 256);
+  o.nslices = (dim + 63) / 64;
+  o.nbr_slots = (L >= 2 && o.nslices * 64 * (uint64_t)(L - 1) <= kPeNbrMaxEntries) ? L - 1 : 0;
+  if (o.nbr_slots == 0) {
+    o.off_nbr = o.total = o.off_scnt;
+    return o;
+  }
+  o.off_nbr = o.off_scnt + align_up(sizeof(uint32_t) * (size_t)o.nslices, 256);
+  o.total = o.off_nbr + sizeof(uint32_t) * (size_t)(o.nslices * 64 * (uint64_t)o.nbr_slots);
   return o;
+}
+
+// The bits of s (L of them) in reverse order: swaps of ever larger halves.
+uint32_t reverse_bits_fast(uint32_t s, int L) {
+  s = ((s >> 1) & 0x55555555u) | ((s & 0x55555555u) << 1);
+  s = ((s >> 2) & 0x33333333u) | ((s & 0x33333333u) << 2);
+  s = ((s >> 4) & 0x0F0F0F0Fu) | ((s & 0x0F0F0F0Fu) << 4);
+  s = ((s >> 8) & 0x00FF00FFu) | ((s & 0x00FF00FFu) << 8);
+  s = (s >> 16) | (s << 16);
+  return s >> (32 - L);
 }
 
 kg_status check_pe_shape(int32_t L, int32_t K) {
@@ -1379,6 +1404,13 @@ PeArgs pe_args(const kg_pe* pe) {
   a.reps = reinterpret_cast<const uint32_t*>(t + o.off_reps);
   a.ranks = reinterpret_cast<const uint32_t*>(t + o.off_ranks);
   a.index = reinterpret_cast<const int32_t*>(t + o.off_index);
+  // KG_PE_NO_NEIGHBORS=1 keeps the rank-forming H v (the tests run both forms)
+  const char* nn = getenv("KG_PE_NO_NEIGHBORS");
+  if (o.nbr_slots > 0 && !(nn && nn[0] == '1')) {
+    a.scnt = reinterpret_cast<const uint32_t*>(t + o.off_scnt);
+    a.nbr = reinterpret_cast<const uint32_t*>(t + o.off_nbr);
+    a.nbr_slots = o.nbr_slots;
+  }
   a.L = pe->L;
   a.K = pe->K;
   a.dim = (uint32_t)pe->dim;
@@ -1480,6 +1512,37 @@ kg_status kg_pe_tables_host(int32_t L, int32_t K, void* tables_host, size_t tabl
     return fail(KG_EINVAL, "internal: enumerated %llu states and %lld orbits, expected %llu, %lld",
                 (unsigned long long)seen, (long long)next, (unsigned long long)sector,
                 (long long)dim);
+  if (o.nbr_slots > 0) {
+    // neighbour table: the j-th antiparallel bond q (ascending) of label r
+    // exchanges bits q, q+1; the rank moves by C(q, zeros below q), up when
+    // the zero moves from q to q+1
+    const int S = o.nbr_slots;
+    uint32_t* scnt = reinterpret_cast<uint32_t*>(host + o.off_scnt);
+    uint32_t* nbr = reinterpret_cast<uint32_t*>(host + o.off_nbr);
+    const uint32_t bondmask = (L == 32) ? 0x7FFFFFFFu : ((1u << (L - 1)) - 1u);
+    for (int64_t b = 0; b < dim; ++b) {
+      const uint32_t r = reps[b];
+      const uint64_t rk = ranks[b];
+      const uint32_t zeros = ~r & (uint32_t)full;
+      const bool nb2 = reverse_bits_fast(r, L) != r;
+      uint32_t* row = nbr + (size_t)(b >> 6) * S * 64 + (b & 63);
+      int j = 0;
+      for (uint32_t act = (r ^ (r >> 1)) & bondmask; act; act &= act - 1u, ++j) {
+        const int q = __builtin_ctz(act);
+        const uint64_t dl = P.c[q][__builtin_popcount(zeros & ((1u << q) - 1u))];
+        const uint64_t rk2 = ((r >> q) & 1u) ? rk - dl : rk + dl;
+        const uint32_t s2 = r ^ (3u << q);
+        const bool na2 = reverse_bits_fast(s2, L) != s2;
+        const uint32_t code = (nb2 == na2) ? 1u : (nb2 ? 2u : 3u);
+        if (rk2 >= sector || index[rk2] < 0 || index[rk2] >= dim)
+          return fail(KG_EINVAL, "internal: neighbour of orbit %lld out of range", (long long)b);
+        row[(size_t)j * 64] = (uint32_t)index[rk2] | (code << 30);
+      }
+      for (int i = j; i < S; ++i) row[(size_t)i * 64] = (uint32_t)b;
+      uint32_t& c = scnt[b >> 6];
+      if ((uint32_t)j > c) c = (uint32_t)j;
+    }
+  }
   return ok();
 }
 
@@ -1607,3 +1670,43 @@ kg_status kg_debug_index_map(int32_t L, uint32_t s0, uint32_t count, int32_t* n_
 }
 
 }  // extern "C"
+
+namespace kg {
+
+// Algorithmic bytes of one reduced-basis H v: x read and y written (2 vb), the
+// orbit labels read, and either the labels' ranks (forming the neighbours'
+// ranks in the kernel) or the neighbour slots the slices use (64 of 4 bytes per
+// slot).  The slot total is counted once per (L, K) by enumerating the orbit
+// labels in ascending order, as the table builder does.
+double pe_gather_bytes(const PeArgs& p, double vb) {
+  const double labels = 4.0 * (double)p.dim;
+  if (!p.nbr) return 2.0 * vb + 2.0 * labels;
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, uint64_t> slots;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = slots.find({p.L, p.K});
+  if (it == slots.end()) {
+    const int L = p.L, ones = L - p.K;
+    const uint64_t full = (L == 32) ? 0xFFFFFFFFull : ((1ull << L) - 1ull);
+    const uint32_t bondmask = (L == 32) ? 0x7FFFFFFFu : ((1u << (L - 1)) - 1u);
+    uint64_t v = ones ? ((1ull << ones) - 1ull) : 0ull, row = 0, total = 0;
+    uint32_t cmax = 0;
+    while (true) {
+      const uint32_t s = (uint32_t)v;
+      if (s <= reverse_bits_fast(s, L)) {
+        cmax = std::max(cmax, (uint32_t)__builtin_popcount((s ^ (s >> 1)) & bondmask));
+        if ((++row & 63u) == 0u) { total += cmax; cmax = 0; }
+      }
+      if (ones == 0) break;
+      const uint64_t c = v & (~v + 1ull);
+      const uint64_t r = v + c;
+      v = (((r ^ v) >> 2) / c) | r;
+      if (v > full) break;
+    }
+    if (row & 63u) total += cmax;
+    it = slots.emplace(std::make_pair(p.L, p.K), total).first;
+  }
+  return 2.0 * vb + labels + 256.0 * (double)it->second;
+}
+
+}  // namespace kg

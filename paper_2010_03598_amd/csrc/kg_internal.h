@@ -123,11 +123,22 @@ struct PeArgs {
   const uint32_t* ranks;   // combinatorial rank of each representative
   const int32_t* index;    // basis index of a sector state's orbit, by combinatorial rank
   const uint32_t* binom;   // C(n, k) at [n * kPeBinom + k], n, k <= 32
+  // neighbour table (nullptr when the basis has none, see kPeNbrMaxEntries):
+  // slot counts per slice of 64 rows, and slot j of row 64 s + l at
+  // nbr[(s * nbr_slots + j) * 64 + l] = orbit | weight code << 30
+  const uint32_t* scnt;
+  const uint32_t* nbr;
+  int32_t nbr_slots;       // L - 1 when the table is there
   int32_t L, K;
   uint32_t dim;
   uint32_t nsec;           // C(L, K): entries of `index`
 };
 constexpr int kPeBinom = 33;
+// The neighbour table is built for bases whose table has at most this many
+// slots (64 per slice and bond: 4 GiB); beyond, H v forms the ranks itself.
+constexpr uint64_t kPeNbrMaxEntries = 1ull << 30;
+// Algorithmic bytes of one reduced-basis H v on vectors of vb bytes.
+double pe_gather_bytes(const PeArgs& p, double vb);
 
 struct KrylovCall {
   HvArgs hv;

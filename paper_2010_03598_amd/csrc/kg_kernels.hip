@@ -228,6 +228,90 @@ __global__ void __launch_bounds__(256) k_hv_pe(HvArgs a, PeArgs p,
   }
 }
 
+// The same H v from the neighbour table built with the basis: a wavefront takes
+// the 64 rows of a slice, reads the slice's slot count (one scalar load), then
+// its rows' entries slot by slot (256 contiguous bytes per slot) and gathers
+// the amplitudes they name, kPeNbrHops slots at a time.  The entries of a row
+// follow its bonds in ascending order, so the sums are those of pe_row, bit
+// for bit.  Slices are dealt to the XCDs in contiguous ranges, so that the
+// near neighbours of low bonds are in the XCD's own L2.
+constexpr int kPeNbrHops = 8;
+
+template <typename R, typename XAt>
+__device__ __forceinline__ void pe_row_nbr(const HvArgs& a, const PeArgs& p, double u, uint32_t s,
+                                           uint32_t b, uint32_t lane, XAt xat, R& yr, R& yi,
+                                           bool& bad) {
+  using V = typename VT<R>::T;
+  const int L = p.L;
+  const uint32_t bondmask = (1u << (L - 1)) - 1u;   // L <= 31 when the table exists
+  const R hJ = (R)a.half_J, czz = (R)a.c_zz, uR = (R)u;
+  const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
+  const uint32_t r = p.reps[b];
+  const int n_anti = (int)__popc((r ^ (r >> 1)) & bondmask);
+  R d = czz * (R)(L - 1 - 2 * n_anti);
+  if (a.hc_kind == 1) d += uR * ((R)(0.5 * a.sz_count) - (R)__popc(r & a.sz_mask));
+  const V xb = xat(b);
+  yr = d * xb.x;
+  yi = d * xb.y;
+  bad = false;
+  const uint32_t c = min(uniform_u32(p.scnt[s]), (uint32_t)p.nbr_slots);
+  const uint32_t* e = p.nbr + (size_t)s * (uint32_t)p.nbr_slots * 64u + lane;
+  for (uint32_t j0 = 0; j0 < c; j0 += kPeNbrHops) {
+    uint32_t ent[kPeNbrHops];
+#pragma unroll
+    for (int j = 0; j < kPeNbrHops; ++j) ent[j] = (j0 + j < c) ? e[(size_t)(j0 + j) * 64u] : b;
+    V xa[kPeNbrHops];
+#pragma unroll
+    for (int j = 0; j < kPeNbrHops; ++j) {
+      const uint32_t ai = ent[j] & 0x3FFFFFFFu;
+      const bool ok = ai < p.dim;
+      bad = bad || !ok;
+      xa[j] = xat(ok ? ai : b);
+    }
+#pragma unroll
+    for (int j = 0; j < kPeNbrHops; ++j) {
+      const uint32_t code = ent[j] >> 30;
+      const R w = code == 0u ? (R)0 : (code == 1u ? (R)1 : (code == 2u ? rt2 : irt2));
+      yr += hJ * w * xa[j].x;
+      yi += hJ * w * xa[j].y;
+    }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_hv_pe_nbr(HvArgs a, PeArgs p,
+                                                   const typename VT<R>::T* __restrict__ x,
+                                                   typename VT<R>::T* __restrict__ y) {
+  using V = typename VT<R>::T;
+  const double u = control_value(a);
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wv = uniform_u32(threadIdx.x >> 6);
+  const uint32_t ns = (p.dim + 63u) >> 6;
+  uint32_t hi = ns, s0 = blockIdx.x * 4u + wv, stride = gridDim.x * 4u;
+  if ((gridDim.x & 7u) == 0u) {
+    // contiguous slices per XCD (blocks are dealt to the 8 XCDs round robin)
+    const uint32_t chunk = (ns + 7u) >> 3;
+    const uint32_t lo = (blockIdx.x & 7u) * chunk;
+    hi = min(lo + chunk, ns);
+    s0 = lo + (blockIdx.x >> 3) * 4u + wv;
+    stride = (gridDim.x >> 3) * 4u;
+  }
+  for (uint32_t s = s0; s < hi; s += stride) {
+    const uint32_t b = (s << 6) | lane;
+    const bool in = b < p.dim;
+    R yr, yi;
+    bool bad;
+    pe_row_nbr<R>(a, p, u, s, in ? b : p.dim - 1u, lane, [&](uint32_t i) { return x[i]; }, yr, yi,
+                  bad);
+    if (in) {
+      V o;
+      o.x = bad ? (R)NAN : yr;
+      o.y = bad ? (R)NAN : yi;
+      y[b] = o;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------- Lanczos passes
 
 struct LzArgs {
@@ -1194,6 +1278,15 @@ hipError_t launch_hv_t(const HvArgs& a, const Geo& g, const void* v, void* w, hi
 template <typename R>
 hipError_t launch_hv_pe_t(const HvArgs& a, const PeArgs& p, const void* v, void* w, hipStream_t s) {
   using V = typename VT<R>::T;
+  if (p.nbr) {
+    // one slice per wavefront: blocks of four, a multiple of 8 for the XCD split
+    const uint32_t ns = (p.dim + 63u) >> 6;
+    uint32_t blocks = ((ns + 3u) / 4u + 7u) & ~7u;
+    if (blocks < 64u) blocks = (ns + 3u) / 4u;
+    kg_launch((k_hv_pe_nbr<R>), dim3(blocks), dim3(256), 0, s, a, p, reinterpret_cast<const V*>(v),
+              reinterpret_cast<V*>(w));
+    return hipGetLastError();
+  }
   uint32_t blocks = (p.dim + 255u) / 256u;
   // grid-stride beyond 8192 blocks (the binomials are staged per block); at
   // 2.6 million rows 8192 blocks were 6 % faster than 2048
@@ -1630,8 +1723,7 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
         if (prof) profiler_start(prof, s);
         if ((e = launch_hv_pe_t<R>(lb.job[j].hv, *calls[j].pe, xk, yk, s)) != hipSuccess)
           return e;
-        // x read, y written, and the orbit label and rank of every output read
-        if (prof) profiler_stop(prof, s, kProfHv, (vb / n) * 2.0 + (double)c0.geo.D * 8.0);
+        if (prof) profiler_stop(prof, s, kProfHv, pe_gather_bytes(*calls[j].pe, vb / n));
       }
     }
     if (prof) profiler_start(prof, s);

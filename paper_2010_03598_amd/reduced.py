@@ -24,7 +24,9 @@ def pe_dim(L: int, K: int) -> int:
 
 def pe_tables_host(L: int, K: int) -> dict:
     """The tables as kg_pe_tables_host writes them (host memory, no device):
-    binom (33 x 33), reps (dim,), ranks (dim,), index (C(L, K),)."""
+    binom (33 x 33), reps (dim,), ranks (dim,), index (C(L, K),) and, when the
+    basis has a neighbour table, slot_counts (slices,) and neighbors
+    (slices, L - 1, 64)."""
     lib = _lib.load()
     nb = int(lib.kg_pe_tables_bytes(int(L), int(K)))
     if nb == 0:
@@ -38,10 +40,17 @@ def pe_tables_host(L: int, K: int) -> dict:
     off_ranks = off_reps + R
     off_index = off_ranks + R
     from math import comb
-    return {"binom": buf[:4 * 33 * 33].view(np.uint32).reshape(33, 33),
-            "reps": buf[off_reps:off_reps + 4 * dim].view(np.uint32),
-            "ranks": buf[off_ranks:off_ranks + 4 * dim].view(np.uint32),
-            "index": buf[off_index:off_index + 4 * comb(L, K)].view(np.int32)}
+    out = {"binom": buf[:4 * 33 * 33].view(np.uint32).reshape(33, 33),
+           "reps": buf[off_reps:off_reps + 4 * dim].view(np.uint32),
+           "ranks": buf[off_ranks:off_ranks + 4 * dim].view(np.uint32),
+           "index": buf[off_index:off_index + 4 * comb(L, K)].view(np.int32)}
+    off_cnt = off_index + (4 * comb(L, K) + 255) // 256 * 256
+    ns = (dim + 63) // 64
+    if off_cnt < nb:
+        off_nbr = off_cnt + (4 * ns + 255) // 256 * 256
+        out["slot_counts"] = buf[off_cnt:off_cnt + 4 * ns].view(np.uint32)
+        out["neighbors"] = buf[off_nbr:nb].view(np.uint32).reshape(ns, L - 1, 64)
+    return out
 
 
 class ReducedBasis:

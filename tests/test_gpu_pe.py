@@ -31,6 +31,17 @@ def oracle_chain(t):
     return pe.PEChain(t.L, t.K, t.J, t.Delta, t.hc_sites)
 
 
+@pytest.fixture(params=["table", "ranks"])
+def gather(request, monkeypatch):
+    """Both forms of the reduced H v: through the basis's neighbour table, and
+    forming the neighbours' ranks in the kernel (KG_PE_NO_NEIGHBORS=1)."""
+    if request.param == "ranks":
+        monkeypatch.setenv("KG_PE_NO_NEIGHBORS", "1")
+    else:
+        monkeypatch.delenv("KG_PE_NO_NEIGHBORS", raising=False)
+    return request.param
+
+
 def task_vectors(t, B):
     e1 = np.zeros(B.dim, dtype=np.complex128)
     eD = np.zeros(B.dim, dtype=np.complex128)
@@ -41,7 +52,7 @@ def task_vectors(t, B):
 
 @pytest.mark.parametrize("L,K", [(6, 3), (7, 3), (10, 3), (13, 3), (14, 7), (16, 8), (17, 6)])
 @pytest.mark.parametrize("dtype", [C128, C64])
-def test_apply_vs_oracle(L, K, dtype):
+def test_apply_vs_oracle(L, K, dtype, gather):
     t = workloads.pe_task(L, K, 1)
     ch = oracle_chain(t)
     x = rand_vec(L * 100 + K, ch.dim)
@@ -54,7 +65,7 @@ def test_apply_vs_oracle(L, K, dtype):
     assert np.abs(y - ref).max() <= tol * np.abs(ref).max()
 
 
-def test_apply_full_size_sampled():
+def test_apply_full_size_sampled(gather):
     """L=25, K=12 (2,600,612 amplitudes): sampled rows against the oracle."""
     t = workloads.pe_large()
     Bo = pe.PEBasis(t.L, t.K)
@@ -70,9 +81,27 @@ def test_apply_full_size_sampled():
     assert np.abs(y64[rows] - ref).max() <= 1e-6 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("L,K", [(25, 12), (17, 6), (28, 2)])
+def test_gather_forms_agree_bit_for_bit(L, K, monkeypatch):
+    """The neighbour table lists a row's bonds in ascending order, so both forms
+    add the same terms in the same order: equal outputs, in both precisions."""
+    t = workloads.pe_task(L, K, 1)
+    B = kg.ReducedBasis(L, K)
+    assert "neighbors" in kg.pe_tables_host(L, K) or L > 28
+    x = rand_vec(L * 7 + K, B.dim)
+    for dtype in (C128, C64):
+        xd = dev_vec(x, dtype)
+        monkeypatch.delenv("KG_PE_NO_NEIGHBORS", raising=False)
+        y_tab = host(kg.xxz_pe_apply(xxz(t), B, 0.29, xd))
+        monkeypatch.setenv("KG_PE_NO_NEIGHBORS", "1")
+        y_rk = host(kg.xxz_pe_apply(xxz(t), B, 0.29, xd))
+        assert np.array_equal(y_tab, y_rk)
+        assert np.isfinite(y_tab).all()
+
+
 @pytest.mark.parametrize("L,K,m", [(10, 3, 10), (13, 3, 10), (16, 8, 12), (6, 3, 16), (5, 0, 4)])
 @pytest.mark.parametrize("dtype", [C128, C64])
-def test_krylov_vs_oracle(L, K, m, dtype):
+def test_krylov_vs_oracle(L, K, m, dtype, gather):
     """Including m beyond the dimension (breakdown: m_eff = dim) and dim = 1."""
     t = workloads.pe_task(L, K, 1)
     ch = oracle_chain(t)
@@ -106,7 +135,7 @@ def oracle_gradient(ch, t, e1, eD, variant, nodes=3):
 
 @pytest.mark.parametrize("variant", ["zeroth", "centred", "first_order", "quadrature"])
 @pytest.mark.parametrize("dtype", [C128, C64])
-def test_gradient_variants_vs_oracle(variant, dtype):
+def test_gradient_variants_vs_oracle(variant, dtype, gather):
     """The paper's task at D = 44 with M = 4D = 176 slices, dt = 0.5, m = 10."""
     t = workloads.pe_paper(9, 3)
     ch = oracle_chain(t)
@@ -224,7 +253,7 @@ class BruteBasis:
 
 
 @pytest.mark.parametrize("L,K", [(32, 2), (31, 3), (32, 1)])
-def test_apply_at_the_largest_chains(L, K):
+def test_apply_at_the_largest_chains(L, K, gather):
     Bo = BruteBasis(L, K)
     sites = 1 | (1 << (L - 1))
     x = rand_vec(L + K, Bo.dim)

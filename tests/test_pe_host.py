@@ -163,3 +163,55 @@ def test_columns_validation():
     assert lib.kg_columns_states_bytes(ctypes.byref(h), 3, 10, 0, _lib.KG_C64) == \
         3 * lib.kg_states_bytes(ctypes.byref(h), 10, 0, _lib.KG_C64)
     assert lib.kg_columns_states_bytes(ctypes.byref(h), 0, 10, 0, _lib.KG_C64) == 0
+
+
+@pytest.mark.parametrize("L,K", [(2, 1), (3, 1), (5, 0), (6, 3), (7, 3), (8, 4), (9, 2), (10, 3),
+                                 (11, 5), (12, 6), (13, 3)])
+def test_neighbour_table_matches_the_oracle_matrix(L, K):
+    """The neighbour table against the oracle's reduced H: slot j of row b names
+    the orbit of the label with its j-th antiparallel bond (ascending)
+    exchanged, with the weight sqrt(n_b / n_a); the slots of a row add up to the
+    off-diagonal part of the oracle's dense matrix (J = 2, so the flip-flop
+    entries are the weights themselves); unused slots name the row itself with
+    weight 0; a slice's count is the largest number of bonds among its rows.
+    A bond may lead back to the row's own orbit (a label whose exchange gives
+    its mirror image), so the comparison is with H minus its Ising diagonal."""
+    t = tables(L, K)
+    B = pe.PEBasis(L, K)
+    H = pe.dense_pe(B, 2.0, 0.0, 0, 0.0)
+    off = H - np.diag(pe.diag_pe(B, 2.0, 0.0, 0, 0.0))
+    weight = {1: 1.0, 2: np.sqrt(2.0), 3: np.sqrt(0.5)}
+    nbr, cnt = t["neighbors"], t["slot_counts"]
+    assert nbr.shape == ((B.dim + 63) // 64, L - 1, 64)
+    for b in range(B.dim):
+        r = int(B.reps[b])
+        bonds = [p for p in range(L - 1) if ((r >> p) ^ (r >> (p + 1))) & 1]
+        ent = nbr[b // 64, :, b % 64]
+        row = np.zeros(B.dim)
+        for j, p in enumerate(bonds):
+            a, c = int(ent[j] & 0x3FFFFFFF), int(ent[j] >> 30)
+            assert a == int(B.index(np.array([r ^ (3 << p)]))[0])
+            assert weight[c] == pytest.approx(np.sqrt(B.n[b] / B.n[a]), rel=1e-15)
+            row[a] += weight[c]
+        assert np.all(ent[len(bonds):] == b)
+        assert np.allclose(row, off[b].real, rtol=0, atol=1e-15) and not off[b].imag.any()
+    for s in range(len(cnt)):
+        rows = range(64 * s, min(64 * s + 64, B.dim))
+        assert cnt[s] == max(bin((int(B.reps[b]) ^ (int(B.reps[b]) >> 1)) & ((1 << (L - 1)) - 1))
+                             .count("1") for b in rows)
+    tail = B.dim % 64
+    if tail:
+        assert not nbr[-1, :, tail:].any()
+
+
+def test_neighbour_table_only_below_its_limit():
+    lib = _lib.load()
+    for L, K in [(28, 14), (29, 14), (32, 16)]:
+        t_bytes = lib.kg_pe_tables_bytes(L, K)
+        dim = lib.kg_pe_dim(L, K)
+        base = 4608 + 2 * ((4 * dim + 255) // 256 * 256) + (4 * comb(L, K) + 255) // 256 * 256
+        ns = (dim + 63) // 64
+        if ns * 64 * (L - 1) <= 1 << 30:
+            assert t_bytes == base + (4 * ns + 255) // 256 * 256 + 4 * ns * 64 * (L - 1)
+        else:
+            assert t_bytes == base
