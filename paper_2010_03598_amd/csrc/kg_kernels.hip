@@ -779,11 +779,12 @@ __device__ __forceinline__ void bload(const V* __restrict__ p, uint32_t base, ui
   }
 }
 
-template <typename R, int RB, int MODE>
+// NWO > 0 sets the number of window vectors per round trip (else WinSlots).
+template <typename R, int RB, int MODE, int NWO = 0>
 __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
-  constexpr int NW = WinSlots<R, RB>::n;
+  constexpr int NW = NWO > 0 ? NWO : WinSlots<R, RB>::n;
   extern __shared__ unsigned char smem_raw[];
   __shared__ cplx_d tot[kMaxScal];
   __shared__ FinScalars fs;
@@ -920,13 +921,13 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   if (threadIdx.x == 0) a.partials[(size_t)kNormCol * kPartialRows + bl] = cplx_d{tot[2 * nb].re, 0.0};
 }
 
-template <typename R, int RB, int MODE>
+template <typename R, int RB, int MODE, int NWO = 0>
 __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzBatch B) {
   const uint32_t G = B.job[0].geo.grid;
   if (blockIdx.x < G) {
-    pass_b_body<R, RB, MODE>(B.job[0], blockIdx.x, G);
+    pass_b_body<R, RB, MODE, NWO>(B.job[0], blockIdx.x, G);
   } else {
-    pass_b_body<R, RB, MODE>(B.job[1], blockIdx.x - G, G);
+    pass_b_body<R, RB, MODE, NWO>(B.job[1], blockIdx.x - G, G);
   }
 }
 
@@ -1338,6 +1339,16 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
     if (g.small) {
       kg_launch((k_pass_b<R, RB, kBMasked>), grid, block, red, s, lb);
     } else if (pairs) {
+      // 2^11-amplitude complex64 tiles and larger: two window vectors per round
+      // trip instead of four (timed forward sweeps, m = 20: 644 -> 615 us per
+      // Krylov call at L=20, 12.80 -> 12.70 ms at L=24; at the 2^10 tiles of
+      // L=18 two were 1-2 % slower)
+      if constexpr (sizeof(R) == 4 && RB == 2) {
+        if (g.TB >= 11) {
+          kg_launch((k_pass_b<R, RB, kBPairs, 2>), grid, block, red, s, lb);
+          return hipGetLastError();
+        }
+      }
       kg_launch((k_pass_b<R, RB, (sizeof(R) == 4 && RB >= 1) ? kBPairs : kBSlots>), grid, block,
                          red, s, lb);
     } else {
