@@ -81,6 +81,35 @@ __device__ __forceinline__ V ld_masked(const V* p, uint32_t s, bool ok) {
   return ok ? v : V{0, 0};
 }
 
+// A nontemporal load of one amplitude (complex64 or complex128): for vectors
+// streamed once per pass whose whole set does not fit in the Infinity Cache,
+// so that they do not displace lines that will be read again.
+template <typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+  if constexpr (sizeof(V) == 8) {
+    typedef float e2 __attribute__((ext_vector_type(2)));
+    const e2 t = __builtin_nontemporal_load(reinterpret_cast<const e2*>(p));
+    V o;
+    o.x = t.x;
+    o.y = t.y;
+    return o;
+  } else {
+    typedef double e2 __attribute__((ext_vector_type(2)));
+    const e2 t = __builtin_nontemporal_load(reinterpret_cast<const e2*>(p));
+    V o;
+    o.x = t.x;
+    o.y = t.y;
+    return o;
+  }
+}
+
+// The same for two neighbouring complex64 amplitudes (16 bytes, aligned).
+__device__ __forceinline__ float4 ld_stream4(const float4* p) {
+  typedef float e4 __attribute__((ext_vector_type(4)));
+  const e4 t = __builtin_nontemporal_load(reinterpret_cast<const e4*>(p));
+  return float4{t.x, t.y, t.z, t.w};
+}
+
 // The NR amplitudes p[s0 | r << 6] of a thread's slots in a tile.  `full`
 // (the whole tile lies inside the vector) must be the same for the whole
 // block: then the loads are plain and unconditional, so the compiler issues

@@ -19,6 +19,18 @@ constexpr int kPartialRows = kMaxGrid + kMaxGrid / 64;  // block rows + group ro
 // unless the vector has at least kLzManyTiles tiles, where kLzGridLarge blocks
 // stream it faster (Krylov calls at L=23 and 24, complex64: 3 and 4.5 %)
 constexpr int kLzGrid = 512;
+// The Infinity Cache (memory-side cache) of the MI355X.  A Krylov basis of m
+// vectors well beyond it is streamed from HBM at every step, and the
+// streaming passes (pass B, the combination) then load it nontemporally.
+// Timed forward sweeps per Krylov call, plain against nontemporal loads:
+// complex64 m=20 L=22 (671 MB basis) 2.29 -> 2.21 ms, m=24 L=23 6.33 -> 5.87
+// ms, L=24 12.75 -> 11.56 ms; complex128 L=22 4.48 -> 4.04 ms, m=24 L=24
+// 24.4 -> 22.5 ms; but with a basis of 336 MB, partly held by the cache
+// (complex64 L=21, complex128 L=20), 1.12 -> 1.17 and 1.08 -> 1.10 ms.
+constexpr size_t kInfinityCacheBytes = (size_t)256 << 20;
+inline bool streamed_past_cache(int m, uint32_t D, size_t amp_bytes) {
+  return (size_t)m * D * amp_bytes > 2 * kInfinityCacheBytes;
+}
 constexpr int kLzGridLarge = 2048;
 constexpr uint32_t kLzManyTiles = 4096;
 

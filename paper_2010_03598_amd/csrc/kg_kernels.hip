@@ -759,14 +759,16 @@ __device__ __forceinline__ uint32_t bpos(uint32_t base, uint32_t lane, uint32_t 
   }
 }
 
-template <int MODE, int RB, typename V, int NR>
+// NT: nontemporal loads (whole tiles only; see ld_stream).
+template <int MODE, int RB, bool NT = false, typename V, int NR>
 __device__ __forceinline__ void bload(const V* __restrict__ p, uint32_t base, uint32_t lane, uint32_t wv,
                                       uint32_t D, V (&o)[NR]) {
   if constexpr (MODE == kBPairs) {
     static_assert(sizeof(V) == 8 && NR % 2 == 0, "pairs of complex64 amplitudes");
 #pragma unroll
     for (int q = 0; q < NR / 2; ++q) {
-      const float4 v = *reinterpret_cast<const float4*>(p + bpos<MODE, RB>(base, lane, wv, 2 * q));
+      const float4* a = reinterpret_cast<const float4*>(p + bpos<MODE, RB>(base, lane, wv, 2 * q));
+      const float4 v = NT ? ld_stream4(a) : *a;
       o[2 * q] = V{v.x, v.y};
       o[2 * q + 1] = V{v.z, v.w};
     }
@@ -774,13 +776,18 @@ __device__ __forceinline__ void bload(const V* __restrict__ p, uint32_t base, ui
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const uint32_t s = bpos<MODE, RB>(base, lane, wv, r);
-      o[r] = (MODE == kBSlots) ? p[s] : ld_masked(p, s, s < D);
+      if constexpr (MODE == kBSlots) {
+        o[r] = NT ? ld_stream(p + s) : p[s];
+      } else {
+        o[r] = ld_masked(p, s, s < D);
+      }
     }
   }
 }
 
-// NWO > 0 sets the number of window vectors per round trip (else WinSlots).
-template <typename R, int RB, int MODE, int NWO = 0>
+// NWO > 0 sets the number of window vectors per round trip (else WinSlots);
+// NT streams the vectors with nontemporal loads.
+template <typename R, int RB, int MODE, int NWO = 0, bool NT = false>
 __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   constexpr int NR = 1 << RB;
@@ -837,8 +844,8 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   for (uint32_t it = 0; it < iters; ++it) {
     const uint32_t base = tile_of(a.geo, it, bl, G) << a.geo.TB;
     V yo[NR], xo[NR];
-    bload<MODE, RB>(yv, base, lane, wv, D, yo);
-    bload<MODE, RB>(x, base, lane, wv, D, xo);
+    bload<MODE, RB, NT>(yv, base, lane, wv, D, yo);
+    bload<MODE, RB, NT>(x, base, lane, wv, D, xo);
     double zr[NR], zi[NR];
     {
       const cplx_d c = cf[a.k - a.i0];
@@ -866,7 +873,7 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
       V q[NW][NR];
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
-        if (i + j < a.k) bload<MODE, RB>(slot_ptr<V>(a, i + j), base, lane, wv, D, q[j]);
+        if (i + j < a.k) bload<MODE, RB, NT>(slot_ptr<V>(a, i + j), base, lane, wv, D, q[j]);
       }
 #pragma unroll
       for (int j = 0; j < NW; ++j) {
@@ -921,13 +928,13 @@ __device__ __forceinline__ void pass_b_body(const LzArgs& a, uint32_t bl, uint32
   if (threadIdx.x == 0) a.partials[(size_t)kNormCol * kPartialRows + bl] = cplx_d{tot[2 * nb].re, 0.0};
 }
 
-template <typename R, int RB, int MODE, int NWO = 0>
+template <typename R, int RB, int MODE, int NWO = 0, bool NT = false>
 __global__ void __launch_bounds__(RB >= 3 ? 512 : 1024) k_pass_b(LzBatch B) {
   const uint32_t G = B.job[0].geo.grid;
   if (blockIdx.x < G) {
-    pass_b_body<R, RB, MODE, NWO>(B.job[0], blockIdx.x, G);
+    pass_b_body<R, RB, MODE, NWO, NT>(B.job[0], blockIdx.x, G);
   } else {
-    pass_b_body<R, RB, MODE, NWO>(B.job[1], blockIdx.x - G, G);
+    pass_b_body<R, RB, MODE, NWO, NT>(B.job[1], blockIdx.x - G, G);
   }
 }
 
@@ -965,7 +972,7 @@ struct CombBatch {
 // One chunk of the combination: kStreamUnroll elements per thread, spaced `stride`
 // apart from s0.  FULL: every element exists, so no load or store is masked (kept
 // apart from the masked form so that the two never share a load's registers).
-template <typename R, bool FULL>
+template <typename R, bool FULL, bool NT = false>
 __device__ __forceinline__ void combine_chunk(const typename VT<R>::T* __restrict__ slot0,
                                               const typename VT<R>::T* __restrict__ basis,
                                               typename VT<R>::T* __restrict__ out, const cplx_d* cs,
@@ -988,7 +995,7 @@ __device__ __forceinline__ void combine_chunk(const typename VT<R>::T* __restric
 #pragma unroll
         for (int q = 0; q < kStreamUnroll; ++q) {
           const uint32_t s = s0 + q * stride;
-          v[jj][q] = FULL ? vj[s] : ld_masked(vj, s, s < D);
+          v[jj][q] = FULL ? (NT ? ld_stream(vj + s) : vj[s]) : ld_masked(vj, s, s < D);
         }
       }
     }
@@ -1018,7 +1025,7 @@ __device__ __forceinline__ void combine_chunk(const typename VT<R>::T* __restric
   }
 }
 
-template <typename R>
+template <typename R, bool NT = false>
 __device__ __forceinline__ void combine_body(const CombJob& cj, uint32_t D, uint32_t bl, uint32_t G) {
   using V = typename VT<R>::T;
   __shared__ cplx_d cs[kMaxM];
@@ -1034,7 +1041,7 @@ __device__ __forceinline__ void combine_body(const CombJob& cj, uint32_t D, uint
   for (uint32_t c0 = bl * kStreamBlock; c0 < D; c0 += stride * kStreamUnroll) {
     // block-uniform: every element of the block's chunk exists
     if (c0 + (kStreamBlock - 1) + (kStreamUnroll - 1) * stride < D) {
-      combine_chunk<R, true>(slot0, basis, out, cs, me, c0 + threadIdx.x, stride, D);
+      combine_chunk<R, true, NT>(slot0, basis, out, cs, me, c0 + threadIdx.x, stride, D);
     } else {
       combine_chunk<R, false>(slot0, basis, out, cs, me, c0 + threadIdx.x, stride, D);
     }
@@ -1042,12 +1049,12 @@ __device__ __forceinline__ void combine_body(const CombJob& cj, uint32_t D, uint
   if (cj.m_eff_out && bl == 0 && threadIdx.x == 0) *cj.m_eff_out = me;
 }
 
-template <typename R>
+template <typename R, bool NT = false>
 __global__ void __launch_bounds__(kStreamBlock) k_combine(CombBatch B) {
   if (blockIdx.x < B.grid) {
-    combine_body<R>(B.job[0], B.D, blockIdx.x, B.grid);
+    combine_body<R, NT>(B.job[0], B.D, blockIdx.x, B.grid);
   } else {
-    combine_body<R>(B.job[1], B.D, blockIdx.x - B.grid, B.grid);
+    combine_body<R, NT>(B.job[1], B.D, blockIdx.x - B.grid, B.grid);
   }
 }
 
@@ -1336,6 +1343,8 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
       const LzArgs& q = lb.job[j];
       if (((uintptr_t)q.slot0 | (uintptr_t)q.basis | (uintptr_t)q.yk) % 16) pairs = false;
     }
+    // a basis larger than the Infinity Cache is streamed with nontemporal loads
+    const bool nt = streamed_past_cache(lb.job[0].m, g.D, sizeof(typename VT<R>::T));
     if (g.small) {
       kg_launch((k_pass_b<R, RB, kBMasked>), grid, block, red, s, lb);
     } else if (pairs) {
@@ -1343,16 +1352,19 @@ hipError_t launch_pass(bool pass_a, const LzBatch& lb, int njobs, hipStream_t s)
       // trip instead of four (timed forward sweeps, m = 20: 644 -> 615 us per
       // Krylov call at L=20, 12.80 -> 12.70 ms at L=24; at the 2^10 tiles of
       // L=18 two were 1-2 % slower)
+      constexpr int PM = (sizeof(R) == 4 && RB >= 1) ? kBPairs : kBSlots;
       if constexpr (sizeof(R) == 4 && RB == 2) {
         if (g.TB >= 11) {
-          kg_launch((k_pass_b<R, RB, kBPairs, 2>), grid, block, red, s, lb);
+          if (nt) kg_launch((k_pass_b<R, RB, kBPairs, 2, true>), grid, block, red, s, lb);
+          else kg_launch((k_pass_b<R, RB, kBPairs, 2>), grid, block, red, s, lb);
           return hipGetLastError();
         }
       }
-      kg_launch((k_pass_b<R, RB, (sizeof(R) == 4 && RB >= 1) ? kBPairs : kBSlots>), grid, block,
-                         red, s, lb);
+      if (nt) kg_launch((k_pass_b<R, RB, PM, 0, true>), grid, block, red, s, lb);
+      else kg_launch((k_pass_b<R, RB, PM>), grid, block, red, s, lb);
     } else {
-      kg_launch((k_pass_b<R, RB, kBSlots>), grid, block, red, s, lb);
+      if (nt) kg_launch((k_pass_b<R, RB, kBSlots, 0, true>), grid, block, red, s, lb);
+      else kg_launch((k_pass_b<R, RB, kBSlots>), grid, block, red, s, lb);
     }
   }
   return hipGetLastError();
@@ -1764,7 +1776,10 @@ hipError_t launch_krylov_t(const KrylovCall* calls, const Workspace* const* wss,
   cb.D = D;
   cb.grid = (uint32_t)stream_grid(D);
   if (prof) profiler_start(prof, s);
-  kg_launch((k_combine<R>), dim3(cb.grid * n), dim3(kStreamBlock), 0, s, cb);
+  if (streamed_past_cache(c0.m, D, sizeof(V)))
+    kg_launch((k_combine<R, true>), dim3(cb.grid * n), dim3(kStreamBlock), 0, s, cb);
+  else
+    kg_launch((k_combine<R>), dim3(cb.grid * n), dim3(kStreamBlock), 0, s, cb);
   e = hipGetLastError();
   // m basis vectors read (fewer after a breakdown), v_out written
   if (prof) profiler_stop(prof, s, kProfCombine, (c0.m + 1) * vb);
