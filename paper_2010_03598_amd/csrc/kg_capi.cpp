@@ -986,8 +986,25 @@ int krylov_dimension(const kg_xxz& h, double umax, double dt, int N, double tol,
 
 // Vector traffic of one chain's gradient in amplitude passes: 2N Krylov calls of
 // about m^2 + 3m passes over 2^L amplitudes.
-double chain_work(const kg_chain& c) {
-  return 2.0 * c.N * ((double)c.m * c.m + 3.0 * c.m) * (double)((int64_t)1 << c.h.L);
+// Modelled time (us) of a chain on a team of T workgroups.  Each of its about
+// 2 N m Lanczos steps costs a fixed part (the team barrier and the scalar
+// update) and, for the busiest member, a part per tile it holds that grows
+// with the window (about (m + 6) / 2 vectors on average).  The part per tile
+// fits the heaviest chain of the 64-chain workload alone (L=16, m=11: 359,
+// 180, 92, 49, 28, 17.7 and 13.6 us per step on 1, 2, 4, ..., 64
+// workgroups).  The fixed part is the one that gave the fastest planned
+// launches of that workload: 4-6 us all gave 127 ms; 0-3 us 132-140 ms,
+// 7-8 us 130-131 ms, 12 us 138 ms and 16 us 152 ms (teams by doubling: 150 ms).
+constexpr double kStepFixedUs = 5.0;
+constexpr double kStepTileUs = 0.65;   // per tile and window vector
+
+int64_t chain_tiles(const kg_chain& c) {
+  return std::max<int64_t>(1, ((int64_t)1 << c.h.L) / kBatchTile);
+}
+
+double chain_time(const kg_chain& c, int team) {
+  const int64_t per = (chain_tiles(c) + team - 1) / team;
+  return 2.0 * c.N * c.m * (kStepFixedUs + kStepTileUs * 0.5 * (c.m + 6) * (double)per);
 }
 
 }  // namespace
@@ -1022,26 +1039,31 @@ kg_status kg_batched_plan(kg_chain* chains, int32_t n_chains, const double* umax
       return fail(KG_EINVAL, "chain %d: team_size=%d outside [1, 64]", i, c.team_size);
   }
   if (!keep_teams) {
-    // greedy makespan balancing: one workgroup per chain, then double the team of
-    // the chain with the largest estimated time (work / team; the lowest index on
-    // ties) while its cap and the grid allow it
+    // greedy makespan balancing: one workgroup per chain, then give the chain
+    // with the largest modelled time (the lowest index on ties) the smallest
+    // team that holds fewer tiles per member, while its cap and the grid allow
+    // it.  The slowest chain bounds the launch, so the loop ends when it cannot
+    // be sped up.
     std::vector<int> cap(n_chains);
     int used = n_chains;
     for (int i = 0; i < n_chains; ++i) {
       chains[i].team_size = 1;
-      const int tiles = (int)(((int64_t)1 << chains[i].h.L) / kBatchTile);
-      cap[i] = std::min(max_team, std::max(1, tiles));
+      cap[i] = (int)std::min<int64_t>(max_team, chain_tiles(chains[i]));
     }
     for (;;) {
       int best = 0;
       for (int i = 1; i < n_chains; ++i)
-        if (chain_work(chains[i]) / chains[i].team_size >
-            chain_work(chains[best]) / chains[best].team_size)
+        if (chain_time(chains[i], chains[i].team_size) >
+            chain_time(chains[best], chains[best].team_size))
           best = i;
       kg_chain& c = chains[best];
-      if (c.team_size * 2 > cap[best] || used + c.team_size > n_blocks) break;
-      used += c.team_size;
-      c.team_size *= 2;
+      const int64_t tiles = chain_tiles(c);
+      const int64_t per = (tiles + c.team_size - 1) / c.team_size;
+      if (per <= 1) break;
+      const int next = (int)((tiles + per - 2) / (per - 1));   // ceil(tiles / (per - 1))
+      if (next > cap[best] || used + (next - c.team_size) > n_blocks) break;
+      used += next - c.team_size;
+      c.team_size = next;
     }
   }
   int64_t off_u = 0, off_vec = 0, off_states = 0, off_ws = 0;

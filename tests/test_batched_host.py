@@ -60,26 +60,61 @@ def test_golden_batch_was_computed_with_the_planned_dimensions():
     assert [d.m for d in descs] == [rec["chain"]["m"] for rec in gold["chains"]]
 
 
-def work(c, m):
-    return 2.0 * c.N * (m * m + 3 * m) * (1 << c.L)
+def modelled_time(c, m, team):
+    """The planner's step model: per Lanczos step 5 us fixed plus 0.65 us per
+    tile of the busiest member and window vector ((m + 6) / 2 on average)."""
+    tiles = max(1, (1 << c.L) // TILE)
+    per = -(-tiles // team)
+    return 2.0 * c.N * m * (5.0 + 0.65 * 0.5 * (m + 6) * per)
 
 
-@pytest.mark.parametrize("n_blocks,max_team", [(256, 64), (128, 8), (64, 1), (300, 16)])
+@pytest.mark.parametrize("n_blocks,max_team", [(256, 64), (128, 8), (64, 1), (300, 16), (256, 32)])
 def test_teams_fit_grid_caps_and_balance(n_blocks, max_team):
     chains = workloads.batched()
     st, descs, p = c_plan(chains, n_blocks, max_team)
     assert st == _lib.KG_OK, _lib.last_error()
     teams = [d.team_size for d in descs]
     assert sum(teams) == p.blocks_used <= n_blocks and min(teams) >= 1
+    caps = [min(max_team, max(1, (1 << c.L) // TILE)) for c in chains]
+    assert all(t <= cap for t, cap in zip(teams, caps))
+    # no team is larger than the smallest one holding the same tiles per member
     for c, t in zip(chains, teams):
-        assert t <= min(max_team, max(1, (1 << c.L) // TILE)) and (t & (t - 1)) == 0
-    # the greedy stops at the chain with the largest time per workgroup; growing
-    # its team further is blocked by its cap or by the grid
-    span = [work(c, d.m) / d.team_size for c, d in zip(chains, descs)]
+        tiles = max(1, (1 << c.L) // TILE)
+        assert t == 1 or -(-tiles // (t - 1)) > -(-tiles // t)
+    # the greedy stops at the chain with the largest modelled time: it holds one
+    # tile per member, or the next team that would hold fewer exceeds its cap or
+    # the grid
+    span = [modelled_time(c, d.m, d.team_size) for c, d in zip(chains, descs)]
     i = int(np.argmax(span))
-    cap = min(max_team, max(1, (1 << chains[i].L) // TILE))
-    assert teams[i] * 2 > cap or p.blocks_used + teams[i] > n_blocks
-    assert max(span) <= max(work(c, d.m) for c, d in zip(chains, descs))
+    tiles = max(1, (1 << chains[i].L) // TILE)
+    per = -(-tiles // teams[i])
+    if per > 1:
+        nxt = -(-tiles // (per - 1))
+        assert nxt > caps[i] or p.blocks_used + nxt - teams[i] > n_blocks
+    # one workgroup per chain is never better
+    assert max(span) <= max(modelled_time(c, d.m, 1) for c, d in zip(chains, descs))
+
+
+def test_planned_makespan_beats_power_of_two_teams():
+    """On the 64-chain workload the modelled slowest chain is faster than with
+    teams restricted to powers of two by doubling (the earlier planner)."""
+    chains = workloads.batched()
+    st, descs, p = c_plan(chains, 256, 64)
+    assert st == _lib.KG_OK
+    ms = [d.m for d in descs]
+    planned = max(modelled_time(c, m, d.team_size) for c, m, d in zip(chains, ms, descs))
+    teams = [1] * len(chains)
+    used = len(chains)
+    work = [2.0 * c.N * (m * m + 3 * m) * (1 << c.L) for c, m in zip(chains, ms)]
+    while True:
+        i = max(range(len(chains)), key=lambda j: (work[j] / teams[j], -j))
+        cap = min(64, max(1, (1 << chains[i].L) // TILE))
+        if teams[i] * 2 > cap or used + teams[i] > 256:
+            break
+        used += teams[i]
+        teams[i] *= 2
+    doubling = max(modelled_time(c, m, t) for c, m, t in zip(chains, ms, teams))
+    assert planned < 0.9 * doubling
 
 
 def test_packing_is_contiguous():
