@@ -460,11 +460,13 @@ typedef struct kg_batch_plan {
  *               for |u| <= umax[i], is at most tol / N (m_max if none is).
  *               The paper leaves the dimension to the user and points to
  *               a-posteriori estimates for the choice (App. A);
- *   team_size   with keep_teams = 0: one workgroup per chain, then the team of
- *               the chain with the largest estimated time (2N(m^2 + 3m) 2^L
- *               vector passes over its team size, the lowest index on ties) is
- *               doubled while it stays within min(max_team, 2^L / 1024) and the
- *               grid of n_blocks workgroups;
+ *   team_size   with keep_teams = 0: one workgroup per chain, then the chain
+ *               with the largest modelled time, 2N m (5 + 0.65 (m + 6)/2
+ *               ceil(tiles / team)) microseconds with tiles = 2^L / 1024 (the
+ *               lowest index on ties), gets the smallest team that holds
+ *               fewer tiles per member, while that stays within
+ *               min(max_team, tiles) and the grid of n_blocks workgroups; any
+ *               size from 1 to 64 can result;
  *   team_first, off_u, off_vec, off_states, off_ws
  *               the chains packed one after the other in order (workspace
  *               offsets 256-byte aligned);
