@@ -39,7 +39,10 @@ def oracle_of(c):
                           krylov.default_tol(krylov.EPS_C64))
 
 
-@pytest.mark.parametrize("teams", [None, [1, 1, 1, 1, 1], [1, 2, 1, 2, 4]])
+# [3, 5, 2, 3, 3]: teams of any size (the planner's sizes need not be powers of
+# two), members holding unequal numbers of tiles, and members holding none
+# (chains of 1, 2 or 4 tiles of 2^10 amplitudes)
+@pytest.mark.parametrize("teams", [None, [1, 1, 1, 1, 1], [1, 2, 1, 2, 4], [3, 5, 2, 3, 3]])
 def test_small_batch_vs_oracle(teams):
     ws = small_chains()
     b = batched.Batch(batched.from_workload(ws, m=12), n_blocks=16, teams=teams)
