@@ -243,7 +243,7 @@ __device__ __forceinline__ void pe_row_nbr(const HvArgs& a, const PeArgs& p, dou
                                            bool& bad) {
   using V = typename VT<R>::T;
   const int L = p.L;
-  const uint32_t bondmask = (1u << (L - 1)) - 1u;   // L <= 31 when the table exists
+  const uint32_t bondmask = (1u << (L - 1)) - 1u;   // L <= 32, so the shift is at most 31
   const R hJ = (R)a.half_J, czz = (R)a.c_zz, uR = (R)u;
   const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
   const uint32_t r = p.reps[b];
