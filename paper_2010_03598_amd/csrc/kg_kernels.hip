@@ -279,7 +279,7 @@ __device__ __forceinline__ void pe_row_nbr(const HvArgs& a, const PeArgs& p, dou
 }
 
 template <typename R>
-__global__ void __launch_bounds__(256) k_hv_pe_nbr(HvArgs a, PeArgs p,
+__global__ void __launch_bounds__(512) k_hv_pe_nbr(HvArgs a, PeArgs p,
                                                    const typename VT<R>::T* __restrict__ x,
                                                    typename VT<R>::T* __restrict__ y) {
   using V = typename VT<R>::T;
@@ -287,14 +287,15 @@ __global__ void __launch_bounds__(256) k_hv_pe_nbr(HvArgs a, PeArgs p,
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wv = uniform_u32(threadIdx.x >> 6);
   const uint32_t ns = (p.dim + 63u) >> 6;
-  uint32_t hi = ns, s0 = blockIdx.x * 4u + wv, stride = gridDim.x * 4u;
+  const uint32_t nwv = blockDim.x >> 6;
+  uint32_t hi = ns, s0 = blockIdx.x * nwv + wv, stride = gridDim.x * nwv;
   if ((gridDim.x & 7u) == 0u) {
     // contiguous slices per XCD (blocks are dealt to the 8 XCDs round robin)
     const uint32_t chunk = (ns + 7u) >> 3;
     const uint32_t lo = (blockIdx.x & 7u) * chunk;
     hi = min(lo + chunk, ns);
-    s0 = lo + (blockIdx.x >> 3) * 4u + wv;
-    stride = (gridDim.x >> 3) * 4u;
+    s0 = lo + (blockIdx.x >> 3) * nwv + wv;
+    stride = (gridDim.x >> 3) * nwv;
   }
   for (uint32_t s = s0; s < hi; s += stride) {
     const uint32_t b = (s << 6) | lane;
@@ -1287,11 +1288,13 @@ template <typename R>
 hipError_t launch_hv_pe_t(const HvArgs& a, const PeArgs& p, const void* v, void* w, hipStream_t s) {
   using V = typename VT<R>::T;
   if (p.nbr) {
-    // one slice per wavefront: blocks of four, a multiple of 8 for the XCD split
+    // one slice per wavefront: blocks of eight (the L=25, K=12 centred
+    // gradient 629 -> 624 ms against blocks of four, the gather alone the
+    // same), a multiple of 8 blocks for the XCD split
     const uint32_t ns = (p.dim + 63u) >> 6;
-    uint32_t blocks = ((ns + 3u) / 4u + 7u) & ~7u;
-    if (blocks < 64u) blocks = (ns + 3u) / 4u;
-    kg_launch((k_hv_pe_nbr<R>), dim3(blocks), dim3(256), 0, s, a, p, reinterpret_cast<const V*>(v),
+    uint32_t blocks = ((ns + 7u) / 8u + 7u) & ~7u;
+    if (blocks < 64u) blocks = (ns + 7u) / 8u;
+    kg_launch((k_hv_pe_nbr<R>), dim3(blocks), dim3(512), 0, s, a, p, reinterpret_cast<const V*>(v),
               reinterpret_cast<V*>(w));
     return hipGetLastError();
   }
