@@ -484,7 +484,8 @@ def time_batched(kg, torch, workloads, steps=3, fp64=True):
     nbytes = batched_algorithmic_bytes(chains, b.m)
     out = {"chains": len(chains), "value": len(chains) / sec, "unit": "chain gradient evals/s",
            "ms_per_launch": sec * 1e3, "launches": steps, "team_cap": info["best_cap"],
-           "m": sorted(set(b.m)), "m_per_chain": list(b.m), "element_slices": int(sum(c.N << c.h.L for c in chains)),
+           "m": sorted(set(b.m)), "m_per_chain": list(b.m), "team_per_chain": list(b.teams),
+           "element_slices": int(sum(c.N << c.h.L for c in chains)),
            "algorithmic_GB_per_launch": nbytes / 1e9,
            "algorithmic_GBps": nbytes / sec / 1e9,
            "frac_of_peak": nbytes / sec / 1e9 / HBM_PEAK_GBS,
