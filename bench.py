@@ -131,6 +131,33 @@ def time_hv(kg, torch, L, dtype, reps=50):
             "launches": reps, "timing": "HIP graph of the launches, best of 3 replays"}
 
 
+def time_copy(torch, mib=1024, reps=10):
+    """Measured HBM bandwidth of a plain device copy (torch's copy kernel) of
+    `mib` MiB, larger than the Infinity Cache: bytes read plus bytes written per
+    second over `reps` back-to-back copies between two events (each copy takes
+    well over 100 us, so launch overhead does not enter); the reference the H v
+    fractions are also stated against."""
+    n = mib << 20
+    src = torch.empty(n // 16, dtype=torch.complex128, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(3):
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3 / reps)
+    del src, dst
+    return {"bytes_per_copy": 2 * n, "GBps": 2 * n / best / 1e9,
+            "frac_of_peak": 2 * n / best / 1e9 / HBM_PEAK_GBS,
+            "timing": f"{mib} MiB read and written, {reps} copies between two events, best of 3"}
+
+
 def time_large(kg, torch, workloads, with_fp64=True, plain=True):
     """The large form: L=24 (D = 16,777,216), N=500 slices of dt=0.05, m=24
     with full re-orthogonalisation, checkpoints every 22 slices.  One gradient
@@ -704,6 +731,9 @@ def main():
     hv20 = time_hv(kg, torch, 20, torch.complex64)
     hv24 = time_hv(kg, torch, 24, torch.complex64, reps=20)
     hv24_128 = time_hv(kg, torch, 24, torch.complex128, reps=20)
+    copy_bw = time_copy(torch)
+    for rec in (hv20, hv24, hv24_128):
+        rec["frac_of_copy"] = rec["algorithmic_GBps"] / copy_bw["GBps"]
 
     bat = None if args.no_batched else time_batched(kg, torch, workloads)
     if bat:
@@ -739,7 +769,7 @@ def main():
         "mixed_vs_fp64_error": {"F_rel": errF, "grad_rel_l2": errg, "grad_rel_inf": errg_inf,
                                 "F_fp64": F128},
         "hv": {"L20_c64": hv20, "L24_c64": hv24, "L24_c128": hv24_128,
-               "peak_GBps": HBM_PEAK_GBS},
+               "peak_GBps": HBM_PEAK_GBS, "copy": copy_bw},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": recorded_traffic(dom),
