@@ -734,8 +734,14 @@ def main():
     copy_bw = time_copy(torch)
     for rec in (hv20, hv24, hv24_128):
         rec["frac_of_copy"] = rec["algorithmic_GBps"] / copy_bw["GBps"]
+    # a copy whose buffers fit in the Infinity Cache: the reference for the
+    # cache-resident batched form
+    copy_cached = time_copy(torch, mib=64, reps=100)
 
     bat = None if args.no_batched else time_batched(kg, torch, workloads)
+    if bat:
+        bat["cache_resident_copy_GBps"] = copy_cached["GBps"]
+        bat["frac_of_cache_resident_copy"] = bat["algorithmic_GBps"] / copy_cached["GBps"]
     if bat:
         log(f"batched: {bat['value']:.1f} chain gradient evals/s")
     pe = None if args.no_pe else time_pe(kg, torch, workloads)
