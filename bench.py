@@ -640,6 +640,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-pe", action="store_true", help="skip the reduced-basis leg")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="time only the 64-chain batched launch (no FP64 comparison)")
     ap.add_argument("--only-pe", action="store_true",
                     help="run only the reduced-basis leg (--steps evaluations) and print its JSON")
     ap.add_argument("--hv-only", type=int, default=0, metavar="L",
@@ -676,6 +678,9 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only_batched:
+        print(json.dumps(time_batched(kg, torch, workloads, fp64=False)), flush=True)
+        return
     if args.only_pe:
         print(json.dumps(time_pe(kg, torch, workloads, steps=args.steps)), flush=True)
         return
