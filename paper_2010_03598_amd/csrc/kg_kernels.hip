@@ -1414,12 +1414,16 @@ constexpr int kFusedBlock = 256;
 constexpr int kFusedNA = 4;                                   // amplitudes per thread
 constexpr uint32_t kFusedMaxD = kFusedBlock * kFusedNA;
 constexpr size_t kFusedLds = (size_t)120 << 10;               // bytes of stored vectors
+// with the reduced basis's neighbour lists staged after them (L - 1 slots and
+// a count per row), at most this much dynamic LDS
+constexpr size_t kFusedLdsStaged = (size_t)140 << 10;
 constexpr int kFusedRed = 2 * kMaxM + 4;
 
 struct FusedJob {
   HvArgs hv;
   PeArgs pe;
   int32_t has_pe;
+  int32_t stage;           // reduced basis: neighbour lists staged in LDS
   uint32_t D;
   int32_t m, reorth;
   double t, tol;
@@ -1460,6 +1464,42 @@ __device__ __forceinline__ void full_row(const HvArgs& a, uint32_t s, const type
   }
 }
 
+// The reduced basis in the one-block call: row b's diagonal (H0 + u Hc)_bb and
+// the orbits reached through its antiparallel bonds (ascending, as pe_row
+// takes them), each as a | c << 30 with the weight code c of sqrt(n_b / n_a)
+// (1: 1, 2: sqrt 2, 3: 1/sqrt 2), written to slots j of `ent` (stride D).
+// Returns the number of bonds, or -1 when a table entry is out of range.
+template <typename R>
+__device__ __forceinline__ int pe_stage_row(const HvArgs& a, const PeArgs& p, const uint32_t* sb,
+                                            double u, uint32_t b, uint32_t* ent, uint32_t D,
+                                            R& diag) {
+  const int L = p.L;
+  const uint32_t full = (L == 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+  const uint32_t bondmask = (L >= 2) ? ((1u << (L - 1)) - 1u) : 0u;
+  const uint32_t r = p.reps[b];
+  const uint32_t rank = p.ranks[b];
+  const uint32_t zeros = ~r & full;
+  const bool nb2 = (__brev(r) >> (32 - L)) != r;
+  const int n_anti = (int)__popc((r ^ (r >> 1)) & bondmask);
+  R d = (R)a.c_zz * (R)(L - 1 - 2 * n_anti);
+  if (a.hc_kind == 1) d += (R)u * ((R)(0.5 * a.sz_count) - (R)__popc(r & a.sz_mask));
+  diag = d;
+  if (rank >= p.nsec) return -1;
+  int j = 0;
+  for (uint32_t act = (r ^ (r >> 1)) & bondmask; act; act &= act - 1u, ++j) {
+    const int q = __builtin_ctz(act);
+    const uint32_t dl = sb[q * kPeBinom + __popc(zeros & ((1u << q) - 1u))];
+    const uint32_t rk = (((r >> q) & 1u) == 0u) ? rank + dl : rank - dl;
+    const int32_t ai = (rk < p.nsec) ? p.index[rk] : -1;
+    if ((uint32_t)ai >= p.dim) return -1;
+    const uint32_t s2 = r ^ (3u << q);
+    const bool na2 = (__brev(s2) >> (32 - L)) != s2;
+    const uint32_t code = (nb2 == na2) ? 1u : (nb2 ? 2u : 3u);
+    ent[(size_t)j * D] = (uint32_t)ai | (code << 30);
+  }
+  return j;
+}
+
 // Totals of n <= kFusedRed values that every wavefront has put in wred[w][0, n):
 // tot[j] = sum over the wavefronts in order.  Barriers before and after.
 __device__ __forceinline__ void fused_totals(double (*wred)[kFusedRed], int n, double* tot) {
@@ -1493,8 +1533,23 @@ __global__ void __launch_bounds__(kFusedBlock) k_krylov_fused(FusedBatch B) {
   const V* __restrict__ vin = reinterpret_cast<const V*>(J.v_in);
   V* __restrict__ vout = reinterpret_cast<V*>(J.v_out);
   const double u = control_value(J.hv);
-  if (J.has_pe)
+  // reduced basis: the binomials, then (when staged) every row's neighbour list
+  // and diagonal, so that the steps read nothing but LDS
+  uint32_t* stg = reinterpret_cast<uint32_t*>(smem_raw + (size_t)m * D * sizeof(V));
+  int32_t* scount = reinterpret_cast<int32_t*>(stg + (J.stage ? (size_t)(J.pe.L - 1) * D : 0));
+  R dg[kFusedNA];
+  if (J.has_pe) {
     for (int i = tid; i < kPeBinom * kPeBinom; i += kFusedBlock) sb[i] = J.pe.binom[i];
+    if (J.stage) {
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kFusedNA; ++q) {
+        const uint32_t s = tid + kFusedBlock * q;
+        dg[q] = (R)0;
+        if (s < D) scount[s] = pe_stage_row<R>(J.hv, J.pe, sb, u, s, stg + s, D, dg[q]);
+      }
+    }
+  }
 
   // u_0 = the input; beta0 = ||u_0||
   double nn = 0.0;
@@ -1544,7 +1599,26 @@ __global__ void __launch_bounds__(kFusedBlock) k_krylov_fused(FusedBatch B) {
       const uint32_t s = tid + kFusedBlock * q;
       R hr = (R)0, hi = (R)0;
       if (s < D) {
-        if (J.has_pe) {
+        if (J.has_pe && J.stage) {
+          const int cnt = scount[s];
+          if (cnt < 0) {
+            hr = hi = (R)NAN;
+          } else {
+            const R hJ = (R)J.hv.half_J;
+            const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
+            const V xb = uk[s];
+            hr = dg[q] * xb.x;
+            hi = dg[q] * xb.y;
+            for (int j = 0; j < cnt; ++j) {
+              const uint32_t e = stg[(size_t)j * D + s];
+              const uint32_t code = e >> 30;
+              const R w = (code == 1u) ? (R)1 : (code == 2u ? rt2 : irt2);
+              const V xa = uk[e & 0x3FFFFFFFu];
+              hr += hJ * w * xa.x;
+              hi += hJ * w * xa.y;
+            }
+          }
+        } else if (J.has_pe) {
           bool bad;
           pe_row<R>(J.hv, J.pe, sb, u, s, [&](uint32_t i) { return uk[i]; }, hr, hi, bad);
           if (bad) hr = hi = (R)NAN;
@@ -1678,10 +1752,16 @@ hipError_t launch_fused_t(const KrylovCall* calls, int n, hipStream_t s) {
   const uint64_t bit = (dev < 64) ? (1ull << dev) : 0ull;
   if (!bit || !(raised.load(std::memory_order_acquire) & bit)) {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_krylov_fused<R>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds);
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsStaged);
     if (e != hipSuccess) return e;
     raised.fetch_or(bit, std::memory_order_acq_rel);
   }
+  // the reduced basis's neighbour lists (L - 1 slots and a count per row) are
+  // staged in LDS behind the stored vectors when both fit
+  const KrylovCall& c0 = calls[0];
+  const size_t basis_bytes = (size_t)c0.m * c0.geo.D * sizeof(V);
+  const size_t stage_bytes = c0.pe ? (size_t)c0.pe->L * c0.geo.D * sizeof(uint32_t) : 0;
+  const bool stage = c0.pe && basis_bytes + stage_bytes <= kFusedLdsStaged;
   FusedBatch fb;
   memset(&fb, 0, sizeof(fb));
   for (int j = 0; j < n; ++j) {
@@ -1690,6 +1770,7 @@ hipError_t launch_fused_t(const KrylovCall* calls, int n, hipStream_t s) {
     f.hv = c.hv;
     if (c.pe) f.pe = *c.pe;
     f.has_pe = c.pe ? 1 : 0;
+    f.stage = (stage && c.pe && c.pe->L == c0.pe->L && c.geo.D == c0.geo.D) ? 1 : 0;
     f.D = c.geo.D;
     f.m = c.m;
     f.reorth = c.reorth;
@@ -1699,7 +1780,7 @@ hipError_t launch_fused_t(const KrylovCall* calls, int n, hipStream_t s) {
     f.v_out = c.v_out;
     f.m_eff_out = c.m_eff_out;
   }
-  const size_t lds = (size_t)calls[0].m * calls[0].geo.D * sizeof(V);
+  const size_t lds = basis_bytes + (stage ? stage_bytes : 0);
   hipLaunchKernelGGL((k_krylov_fused<R>), dim3(n), dim3(kFusedBlock), lds, s, fb);
   return hipGetLastError();
 }
