@@ -1410,8 +1410,8 @@ hipError_t launch_pass_r(bool pass_a, const LzBatch& lb, int njobs, hipStream_t 
 // w = y - sum_i c_i s_i u_i in FP64.  The breakdown test and the combination
 // are those of the tiled passes.  Reductions: quad_sums within a wavefront,
 // then the wavefronts in order, so every thread reads the same totals.
-constexpr int kFusedBlock = 256;
-constexpr int kFusedNA = 4;                                   // amplitudes per thread
+constexpr int kFusedBlock = 512;
+constexpr int kFusedNA = 2;                                   // amplitudes per thread
 constexpr uint32_t kFusedMaxD = kFusedBlock * kFusedNA;
 constexpr size_t kFusedLds = (size_t)120 << 10;               // bytes of stored vectors
 // with the reduced basis's neighbour lists staged after them (L - 1 slots and
@@ -1609,6 +1609,7 @@ __global__ void __launch_bounds__(kFusedBlock) k_krylov_fused(FusedBatch B) {
             const V xb = uk[s];
             hr = dg[q] * xb.x;
             hi = dg[q] * xb.y;
+#pragma unroll 4
             for (int j = 0; j < cnt; ++j) {
               const uint32_t e = stg[(size_t)j * D + s];
               const uint32_t code = e >> 30;
