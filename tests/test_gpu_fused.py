@@ -110,11 +110,14 @@ def test_eigenstate_and_degenerate_inputs():
 
 
 @pytest.mark.parametrize("L,K,m", [(6, 3, 10), (7, 3, 10), (9, 3, 10), (10, 3, 10), (13, 3, 10),
-                                   (12, 4, 10), (6, 3, 16), (5, 0, 4)])
+                                   (12, 4, 10), (6, 3, 16), (5, 0, 4), (13, 5, 10), (13, 5, 11)])
 @pytest.mark.parametrize("dtype", [C128, C64])
 def test_reduced_basis_matches_oracle(L, K, m, dtype):
     """The paper's task sizes (dim 10, 19, 44, 60, 146) and D = 255, in the
-    reduced basis, including m beyond the dimension and dim = 1."""
+    reduced basis, including m beyond the dimension and dim = 1.  D = 651
+    (L=13, K=5) in complex128 puts the stored basis and the neighbour lists
+    (4 L D bytes) just inside the 140 KiB of LDS at m = 10 and past it at
+    m = 11, where each step forms the neighbours' ranks from the tables."""
     t = workloads.pe_task(L, K, 1)
     ch = pe.PEChain(t.L, t.K, t.J, t.Delta, t.hc_sites)
     assert fits(ch.dim, m, dtype)
