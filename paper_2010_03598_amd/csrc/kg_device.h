@@ -54,9 +54,12 @@ __device__ __forceinline__ double wave_sum(double v) {
 // Sums of four values over the 64 lanes of a wavefront at once; lane l
 // returns the total of v[l mod 4].  Two halving exchanges within quads (the
 // lane keeps the half its index bit selects and adds the partner's copy of
-// it), then sums over the other index bits.  The order of the additions is
-// fixed.  About a third of the instructions of four wave_sum calls.
-__device__ __forceinline__ double quad_sums(double v0, double v1, double v2, double v3) {
+// it), then sums over the other index bits: rotations by 4 and 8 inside rows
+// of 16 lanes (they keep l mod 4), then exchanges with lane l ^ 16 and
+// l ^ 32.  The order of the additions is fixed.  About a third of the
+// instructions of four wave_sum calls.
+__device__ __forceinline__ double quad_sums_within_rows(double v0, double v1, double v2,
+                                                        double v3) {
   const int lane = threadIdx.x & 63;
   // bit 1: lanes with the bit set keep values 2, 3
   const bool b1 = (lane >> 1) & 1;
@@ -66,10 +69,46 @@ __device__ __forceinline__ double quad_sums(double v0, double v1, double v2, dou
   // bit 0: lanes with the bit set keep the second of the two
   const bool b0 = lane & 1;
   double t = (b0 ? k1 : k0) + dpp_f64<0xB1>(b0 ? k0 : k1);   // quad_perm [1,0,3,2]
-  t += __shfl_xor(t, 4, 64);
-  t += dpp_f64<0x128>(t);   // row_ror:8, lane ^ 8 within rows of 16
+  t += dpp_f64<0x124>(t);   // row_ror:4
+  t += dpp_f64<0x128>(t);   // row_ror:8
+  return t;
+}
+
+// The exchanges across rows through LDS permutes (ds_bpermute).
+__device__ __forceinline__ double quad_sums(double v0, double v1, double v2, double v3) {
+  double t = quad_sums_within_rows(v0, v1, v2, v3);
   t += __shfl_xor(t, 16, 64);
   t += __shfl_xor(t, 32, 64);
+  return t;
+}
+
+// v of lane l ^ 16 (l ^ 32) by the lane-swap instructions, no LDS.  Called
+// with both operands equal, permlane16_swap returns {lanes of odd rows take
+// the even row below, lanes of even rows keep theirs} and {even rows take the
+// odd row above, odd rows keep theirs}; permlane32_swap the same with the
+// wavefront's two halves.
+__device__ __forceinline__ double xor_lanes_16(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const bool up = (threadIdx.x & 16) != 0;
+  return __hiloint2double((int)(up ? b[0] : b[1]), (int)(up ? a[0] : a[1]));
+}
+__device__ __forceinline__ double xor_lanes_32(double v) {
+  const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const bool up = (threadIdx.x & 32) != 0;
+  return __hiloint2double((int)(up ? b[0] : b[1]), (int)(up ? a[0] : a[1]));
+}
+
+// quad_sums with the exchanges across rows by lane swaps.  Faster in the
+// one-block Krylov call; in the tiled passes it made the Lanczos step slower
+// (the LDS-permute form stays there).
+__device__ __forceinline__ double quad_sums_swap(double v0, double v1, double v2, double v3) {
+  double t = quad_sums_within_rows(v0, v1, v2, v3);
+  t += xor_lanes_16(t);
+  t += xor_lanes_32(t);
   return t;
 }
 

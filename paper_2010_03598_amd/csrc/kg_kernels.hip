@@ -1584,53 +1584,57 @@ __global__ void __launch_bounds__(kFusedBlock) k_krylov_fused(FusedBatch B) {
   }
   __syncthreads();
 
+  // Step k takes h = H u_k, its window dots and ||u_k||^2 (of the vector the
+  // previous step stored) in one block reduction; the scale s_k = 1/||u_k||,
+  // the breakdown test on ||u_k|| and then y = s_k h follow from the totals.
   double normT = 0.0;
   int meff = m;
+  double wn_wave = 0.0;   // this wavefront's part of ||u_k||^2 (k >= 1)
   for (int k = 0; k < m; ++k) {
     const bool last = k == m - 1;
     const int i0 = last ? k : (J.reorth ? 0 : (k > 0 ? k - 1 : 0));
     const int nw = k - i0 + 1;
-    const double sk = sc[k];
     const V* uk = ub + (size_t)k * D;
-    // y = s_k H u_k on this thread's rows
-    double yr[kFusedNA], yi[kFusedNA];
+    if (k > 0) __syncthreads();   // every row of u_k is stored
+    // h = H u_k on this thread's rows, in the vector type
+    R hr[kFusedNA], hi[kFusedNA];
 #pragma unroll
     for (int q = 0; q < kFusedNA; ++q) {
       const uint32_t s = tid + kFusedBlock * q;
-      R hr = (R)0, hi = (R)0;
+      hr[q] = (R)0;
+      hi[q] = (R)0;
       if (s < D) {
         if (J.has_pe && J.stage) {
           const int cnt = scount[s];
           if (cnt < 0) {
-            hr = hi = (R)NAN;
+            hr[q] = hi[q] = (R)NAN;
           } else {
             const R hJ = (R)J.hv.half_J;
             const R rt2 = (R)1.4142135623730951, irt2 = (R)0.70710678118654752;
             const V xb = uk[s];
-            hr = dg[q] * xb.x;
-            hi = dg[q] * xb.y;
+            R ar = dg[q] * xb.x, ai = dg[q] * xb.y;
 #pragma unroll 4
             for (int j = 0; j < cnt; ++j) {
               const uint32_t e = stg[(size_t)j * D + s];
               const uint32_t code = e >> 30;
               const R w = (code == 1u) ? (R)1 : (code == 2u ? rt2 : irt2);
               const V xa = uk[e & 0x3FFFFFFFu];
-              hr += hJ * w * xa.x;
-              hi += hJ * w * xa.y;
+              ar += hJ * w * xa.x;
+              ai += hJ * w * xa.y;
             }
+            hr[q] = ar;
+            hi[q] = ai;
           }
         } else if (J.has_pe) {
           bool bad;
-          pe_row<R>(J.hv, J.pe, sb, u, s, [&](uint32_t i) { return uk[i]; }, hr, hi, bad);
-          if (bad) hr = hi = (R)NAN;
+          pe_row<R>(J.hv, J.pe, sb, u, s, [&](uint32_t i) { return uk[i]; }, hr[q], hi[q], bad);
+          if (bad) hr[q] = hi[q] = (R)NAN;
         } else {
-          full_row<R>(J.hv, s, uk, u, hr, hi);
+          full_row<R>(J.hv, s, uk, u, hr[q], hi[q]);
         }
       }
-      yr[q] = sk * (double)hr;
-      yi[q] = sk * (double)hi;
     }
-    // <u_i|y> for the window, two vectors per quad_sums
+    // <u_i|h> for the window, two vectors per quad_sums
     for (int i = i0; i <= k; i += 2) {
       const bool two = i + 1 <= k;
       double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
@@ -1638,36 +1642,59 @@ __global__ void __launch_bounds__(kFusedBlock) k_krylov_fused(FusedBatch B) {
       for (int q = 0; q < kFusedNA; ++q) {
         const uint32_t s = tid + kFusedBlock * q;
         if (s < D) {
+          const double h_r = (double)hr[q], h_i = (double)hi[q];
           const V x0 = ub[(size_t)i * D + s];
-          a0r += (double)x0.x * yr[q] + (double)x0.y * yi[q];
-          a0i += (double)x0.x * yi[q] - (double)x0.y * yr[q];
+          a0r += (double)x0.x * h_r + (double)x0.y * h_i;
+          a0i += (double)x0.x * h_i - (double)x0.y * h_r;
           if (two) {
             const V x1 = ub[(size_t)(i + 1) * D + s];
-            a1r += (double)x1.x * yr[q] + (double)x1.y * yi[q];
-            a1i += (double)x1.x * yi[q] - (double)x1.y * yr[q];
+            a1r += (double)x1.x * h_r + (double)x1.y * h_i;
+            a1i += (double)x1.x * h_i - (double)x1.y * h_r;
           }
         }
       }
-      const double t = quad_sums(a0r, a0i, a1r, a1i);
+      const double t = quad_sums_swap(a0r, a0i, a1r, a1i);
       if (lane < 4u) wred[wv][2 * (i - i0) + lane] = t;
     }
-    fused_totals(wred, 2 * nw, tot);
-    // alpha_k = s_k Re<u_k|y>, the running ||T||
-    const double alpha = sk * tot[2 * (k - i0)];
-    normT = fmax(normT, fabs(alpha) + off[k]);
+    // (slot 2 nw + 2: the pair loop writes at most up to 2 nw + 1)
+    if (lane == 0) wred[wv][2 * nw + 2] = wn_wave;
+    fused_totals(wred, 2 * nw + 3, tot);
+    // s_k, or a breakdown: ||u_k|| small against ||T|| means an invariant
+    // Krylov space of dimension k
+    double sk, offk;
+    if (k == 0) {
+      sk = 1.0 / beta0;
+      offk = 0.0;
+    } else {
+      offk = sqrt(tot[2 * nw + 2]);
+      if (offk <= J.tol * fmax(1.0, normT)) {
+        meff = k;
+        break;
+      }
+      sk = 1.0 / offk;
+      if (tid == 0) {
+        off[k] = offk;
+        sc[k] = sk;
+      }
+    }
+    // alpha_k = s_k Re<u_k|s_k h>, the running ||T||
+    const double alpha = sk * sk * tot[2 * (k - i0)];
+    normT = fmax(normT, fabs(alpha) + offk);
     if (tid == 0) al[k] = alpha;
     if (last) break;
-    // w = y - sum_i c_i s_i u_i with c_i = s_i <u_i|y>, stored as u_{k+1}
+    // w = y - sum_i c_i s_i u_i with y = s_k h and c_i = s_i <u_i|y>, stored
+    // as u_{k+1}
     double wn = 0.0;
     V* uo = ub + (size_t)(k + 1) * D;
 #pragma unroll
     for (int q = 0; q < kFusedNA; ++q) {
       const uint32_t s = tid + kFusedBlock * q;
       if (s < D) {
-        double wr = yr[q], wi = yi[q];
+        double wr = sk * (double)hr[q], wi = sk * (double)hi[q];
         for (int i = i0; i <= k; ++i) {
-          const double si = sc[i];
-          const double cr = si * si * tot[2 * (i - i0)], ci = si * si * tot[2 * (i - i0) + 1];
+          const double si = (i == k) ? sk : sc[i];
+          const double f = si * si * sk;
+          const double cr = f * tot[2 * (i - i0)], ci = f * tot[2 * (i - i0) + 1];
           const V x = ub[(size_t)i * D + s];
           wr -= cr * x.x - ci * x.y;
           wi -= cr * x.y + ci * x.x;
@@ -1679,21 +1706,7 @@ __global__ void __launch_bounds__(kFusedBlock) k_krylov_fused(FusedBatch B) {
         wn += (double)o.x * o.x + (double)o.y * o.y;
       }
     }
-    wn = wave_sum(wn);
-    if (lane == 0) wred[wv][0] = wn;
-    fused_totals(wred, 1, tot);
-    // ||w||: the next off-diagonal entry, or a breakdown (an invariant
-    // Krylov space of dimension k + 1)
-    const double bk = sqrt(tot[0]);
-    if (bk <= J.tol * fmax(1.0, normT)) {
-      meff = k + 1;
-      break;
-    }
-    if (tid == 0) {
-      off[k + 1] = bk;
-      sc[k + 1] = 1.0 / bk;
-    }
-    __syncthreads();
+    wn_wave = wave_sum(wn);
   }
   __syncthreads();
   // exp(-itT) e_1 on wavefront 0 and the combination coefficients beta0 e_j s_j
