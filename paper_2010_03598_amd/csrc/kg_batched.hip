@@ -262,14 +262,37 @@ __device__ bool team_krylov(BCtx& c, const kg_chain& ch, double t, double tol, c
         for (int j = 0; j < 8; ++j)
           if (i + j < k) q[j] = bslot(c, in, i + j)[s];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < 8; j += 2) {
           if (i + j < k) {
-            const double vr = q[j].x, vi = q[j].y;
-            const cplx_d cc = cf[i + j - i0];
-            zr -= cc.re * vr - cc.im * vi;
-            zi -= cc.re * vi + cc.im * vr;
-            add_quad(i + j - i0, nwin + i + j - i0,
-                     quad_sums(vr * yr + vi * yi, vr * yi - vi * yr, vr * xr + vi * xi, vr * xi - vi * xr));
+            double d4[2][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              d4[h][0] = d4[h][1] = d4[h][2] = d4[h][3] = 0.0;
+              if (i + j + h < k) {
+                const double vr = q[j + h].x, vi = q[j + h].y;
+                const cplx_d cc = cf[i + j + h - i0];
+                zr -= cc.re * vr - cc.im * vi;
+                zi -= cc.re * vi + cc.im * vr;
+                d4[h][0] = vr * yr + vi * yi;
+                d4[h][1] = vr * yi - vi * yr;
+                d4[h][2] = vr * xr + vi * xi;
+                d4[h][3] = vr * xi - vi * xr;
+              }
+            }
+            const double tq = quad_sums_pair(d4[0][0], d4[0][1], d4[0][2], d4[0][3], d4[1][0],
+                                             d4[1][1], d4[1][2], d4[1][3]);
+            // lanes 0..3: vector i + j; lanes 4..7: vector i + j + 1
+            const int h = (int)((lane >> 2) & 1u);
+            if (lane < 8u && i + j + h < k) {
+              const uint32_t l4 = lane & 3u;
+              const int w = i + j + h - i0;
+              cplx_d& d = wrow[l4 < 2u ? w : nwin + w];
+              if (l4 & 1u) {
+                d.im += tq;
+              } else {
+                d.re += tq;
+              }
+            }
           }
         }
       }

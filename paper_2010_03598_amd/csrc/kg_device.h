@@ -82,6 +82,21 @@ __device__ __forceinline__ double quad_sums(double v0, double v1, double v2, dou
   return t;
 }
 
+// Two quad_sums with one exchange across rows: lane l returns the total of
+// a[l mod 4] where bit 2 of l is clear and of b[l mod 4] where it is set
+// (after the sums within rows every lane of a row holds its row's totals, so
+// half of a row can carry b).  Faster in the batched kernel; in pass B of the
+// tiled form it made the step slower.
+__device__ __forceinline__ double quad_sums_pair(double a0, double a1, double a2, double a3,
+                                                 double b0, double b1, double b2, double b3) {
+  const double ta = quad_sums_within_rows(a0, a1, a2, a3);
+  const double tb = quad_sums_within_rows(b0, b1, b2, b3);
+  double t = ((threadIdx.x >> 2) & 1u) ? tb : ta;
+  t += __shfl_xor(t, 16, 64);
+  t += __shfl_xor(t, 32, 64);
+  return t;
+}
+
 // v of lane l ^ 16 (l ^ 32) by the lane-swap instructions, no LDS.  Called
 // with both operands equal, permlane16_swap returns {lanes of odd rows take
 // the even row below, lanes of even rows keep theirs} and {even rows take the
