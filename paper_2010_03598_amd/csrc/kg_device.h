@@ -191,10 +191,18 @@ __device__ __forceinline__ double lane_value(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
+// Maximum over the 64 lanes of values >= 0 (a lane outside a DPP source
+// reads +0.0), the same value in every lane: the DPP steps of wave_sum.
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x124>(v));
+  v = fmax(v, dpp_f64<0x128>(v));
+  v = fmax(v, dpp_f64<0x142, 0xA>(v));
+  v = fmax(v, dpp_f64<0x143, 0xC>(v));
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ void st_agent(double* p, double v) {

@@ -1398,18 +1398,22 @@ hipError_t launch_pass_r(bool pass_a, const LzBatch& lb, int njobs, hipStream_t 
 // D <= kFusedMaxD amplitudes and m D amplitudes of LDS at most kFusedLds
 // bytes.  At such sizes the tiled form is a chain of about 2m dependent
 // launches of one block each, bound by their latency; here the basis never
-// leaves LDS and a step costs a few block barriers.
+// leaves LDS and a step costs one block reduction and three barriers.
 //
 // Thread t owns amplitudes (rows) t + kFusedBlock a.  The stored vectors
 // are u_0 = the input as given and u_{k+1} = w_{k+1} rounded to the vector
 // type, unnormalised, with their scales s_k = 1/||u_k|| kept in FP64; step k
-// forms y = s_k H u_k (accumulated in the vector type, as the tiled H v),
-// takes the projection coefficients c_i = s_i <u_i|y> against the same y
-// over the window (classical Gram-Schmidt: every stored vector with full
-// re-orthonormalisation, the last two without), alpha_k = s_k Re<u_k|y>, and
-// w = y - sum_i c_i s_i u_i in FP64.  The breakdown test and the combination
-// are those of the tiled passes.  Reductions: quad_sums within a wavefront,
-// then the wavefronts in order, so every thread reads the same totals.
+// forms h = H u_k (accumulated in the vector type, as the tiled H v) and
+// reduces its window dots together with ||u_k||^2, then takes s_k (or the
+// breakdown), y = s_k h, the projection coefficients c_i = s_i <u_i|y>
+// against the same y over the window (classical Gram-Schmidt: every stored
+// vector with full re-orthonormalisation, the last two without),
+// alpha_k = s_k Re<u_k|y>, and w = y - sum_i c_i s_i u_i in FP64.  The
+// breakdown test and the combination are those of the tiled passes.
+// Reductions: quad_sums_swap within a wavefront, then the wavefronts in
+// order, so every thread reads the same totals.  For the reduced basis the
+// rows' neighbour lists are staged in LDS behind the stored vectors when
+// both fit in kFusedLdsStaged bytes.
 constexpr int kFusedBlock = 512;
 constexpr int kFusedNA = 2;                                   // amplitudes per thread
 constexpr uint32_t kFusedMaxD = kFusedBlock * kFusedNA;
